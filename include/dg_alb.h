@@ -1,0 +1,203 @@
+/*
+ * dg_alb.h -- batched adaptive-local-basis (ALB) generation on one AMD MI355X.
+ *
+ * The library solves, for a batch of extended elements Q_k, the local
+ * Kohn-Sham eigenproblem of Eq. (1) (LocalKS)
+ *
+ *     H^{Q_k} phi = (-1/2 Laplacian + V_eff + sum_{I,l} gamma_{I,l} |b_{I,l}><b_{I,l}|) phi
+ *                 = lambda phi
+ *
+ * in the plane-wave basis of the periodic box Q_k (every grid plane wave,
+ * Nyquist mode included), for the lowest J_k eigenpairs ("Generating ALB
+ * functions" subsection), by LOBPCG (Algorithm 1, Eqs. (2)-(4)) or by
+ * Chebyshev-filtered subspace iteration (Algorithm 2 and Eqs. (8)-(9),
+ * applied to H^{Q_k}), then restricts the eigenvectors to the element E_k and
+ * orthonormalises them there into ALBs.
+ *
+ * Conventions (all entry points):
+ *  - Grid vectors are real FP64 or FP32 arrays of N = n[0]*n[1]*n[2] values,
+ *    x fastest: index = x + n[0]*(y + n[1]*z).  Vectors are Euclidean
+ *    normalised on the grid (x^T x = 1).
+ *  - "Packed" blocks hold, element after element, an N_k x m_k column-major
+ *    matrix with leading dimension N_k (one state per contiguous column).
+ *    dg_query_offsets gives the start of each element's block.
+ *  - Pointers named *_dev are device pointers (HBM), *_host are host
+ *    pointers.  Device buffers are owned by the caller and must stay alive
+ *    until the work queued on the context's stream has completed.
+ *  - Every function returns a dg_status.  Negative = error, no output is
+ *    valid.  Positive = warning, outputs are valid.  No exception or abort
+ *    crosses the interface.  dg_last_error() describes the last failure on
+ *    the calling thread.
+ *  - A context is bound to one HIP stream and is not thread-safe.  The
+ *    library never allocates device memory: the caller provides one arena of
+ *    the size dg_query_workspace reports.
+ */
+#ifndef DG_ALB_H
+#define DG_ALB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+enum dg_status {
+  DG_OK = 0,
+  DG_WARN_NOT_CONVERGED = 1, /* outputs valid; residuals above tolerance */
+  DG_ERR_ARG = -1,           /* invalid argument (NULL, out of range)   */
+  DG_ERR_SHAPE = -2,         /* unsupported grid / sizes                */
+  DG_ERR_OOM = -3,           /* arena too small                         */
+  DG_ERR_HIP = -4,           /* HIP runtime error (see dg_last_error)   */
+  DG_ERR_NUMERIC = -5,       /* NaN/Inf or unrecoverable breakdown      */
+  DG_ERR_STATE = -6          /* call out of order (e.g. ALB before solve) */
+};
+
+enum dg_prec {
+  DG_FP64 = 0,  /* every step in FP64                                            */
+  DG_MIXED = 1, /* FP32 H*psi and subspace GEMMs, FP64 small dense; then FP64    */
+                /* refinement sweeps to the requested tolerance                  */
+  DG_FP32 = 2   /* FP32 H*psi (dg_apply_H, dg_band_energy only)                  */
+};
+
+enum dg_method {
+  DG_LOBPCG = 0, /* Algorithm 1 */
+  DG_CHFSI = 1   /* Algorithm 2 applied to H^{Q_k} */
+};
+
+/* One extended element Q_k (Eq. (1)); host pointers, copied by dg_create_elements. */
+typedef struct {
+  int32_t n[3];        /* grid points of Q_k along x, y, z                         */
+  double len[3];       /* box lengths (bohr); grid spacing len[i]/n[i]             */
+  int32_t elem_lo[3];  /* first grid point of E_k inside Q_k                       */
+  int32_t elem_n[3];   /* grid points of E_k                                       */
+  int32_t n_states;    /* J_k wanted eigenpairs                                    */
+  const double *v_eff; /* N values of V_eff on Q_k (Ha)                            */
+  int32_t n_proj;      /* number of projectors b_{I,l} with support in Q_k         */
+  const int64_t *proj_ptr; /* n_proj+1 offsets into proj_idx / proj_val (CSC of B) */
+  const int32_t *proj_idx; /* grid indices, strictly ascending within a projector  */
+  const double *proj_val;  /* b_{I,l} values                                       */
+  const double *gamma;     /* n_proj weights gamma_{I,l} (Ha)                      */
+} dg_element_desc;
+
+typedef struct {
+  int32_t n_guard;        /* guard states carried above J_k; < 0: max(4, ceil(J_k/10)) */
+  int32_t max_cheb_degree;/* largest Chebyshev degree used by dg_band_energy (0: none)  */
+  int32_t ckpt_stride;    /* checkpoint every ckpt_stride filter steps (>= 1)           */
+  int32_t reserved;
+} dg_options;
+
+typedef struct {
+  int32_t method;      /* dg_method                                                   */
+  int32_t precision;   /* DG_FP64 or DG_MIXED                                         */
+  double tol;          /* converged when max_i ||H x_i - theta_i x_i||_2 <= tol (Ha)  */
+                       /* over the J_k wanted states of every element                */
+  double tol_mixed;    /* DG_MIXED: residual at which the FP32 stage hands over to    */
+                       /* FP64 refinement (<= 0: 1e-4)                                */
+  int32_t max_iter;    /* iteration cap per stage                                     */
+  int32_t cheb_degree; /* DG_CHFSI filter degree m                                    */
+  const double *x0_dev;/* packed initial blocks, N_k x (J_k + guards) per element     */
+                       /* (dg_query_offsets(DG_OFF_X0)); need not be orthonormal      */
+} dg_solve_params;
+
+enum dg_offset_kind {
+  DG_OFF_X0 = 0,   /* packed N_k x (J_k+g_k) blocks (x0_dev)            */
+  DG_OFF_VEC = 1,  /* packed N_k x J_k blocks (dg_get_vectors)           */
+  DG_OFF_EIG = 2,  /* J_k values per element (eigenvalues, residuals)    */
+  DG_OFF_ALB = 3,  /* packed |E_k| x J_k blocks (dg_make_alb)            */
+  DG_OFF_GRID = 4, /* N_k values per element (V, dE/dV)                  */
+  DG_OFF_KALL = 5  /* J_k+g_k values per element                         */
+};
+
+/* Human-readable name of a status code (static string). */
+const char *dg_status_string(int32_t status);
+
+/* Description of the last error on the calling thread (ctx may be NULL). */
+const char *dg_last_error(const dg_ctx *ctx);
+
+/* Arena bytes needed for these elements and options.  CPU only: validates the
+ * descriptors and never touches the GPU.  Errors: DG_ERR_ARG, DG_ERR_SHAPE. */
+int32_t dg_query_workspace(int32_t n_elem, const dg_element_desc *elems,
+                           const dg_options *opt, size_t *bytes);
+
+/* Create a context: copies the element data (Eq. (1)'s V_eff, b, gamma and the
+ * E_k boxes) into the caller's device arena on hip_stream, and builds the
+ * batch plan.  dev_arena must hold arena_bytes >= dg_query_workspace's value,
+ * 256-byte aligned.  *ctx is set on success and must be released with
+ * dg_destroy.  Errors: DG_ERR_ARG, DG_ERR_SHAPE, DG_ERR_OOM, DG_ERR_HIP. */
+int32_t dg_create_elements(dg_ctx **ctx, int32_t n_elem, const dg_element_desc *elems,
+                           const dg_options *opt, void *dev_arena, size_t arena_bytes,
+                           void *hip_stream);
+
+/* Release the context (host memory only; the arena stays the caller's). */
+void dg_destroy(dg_ctx *ctx);
+
+/* Offsets (in elements of the block's value type) of each element's part of a
+ * packed buffer, n_elem + 1 values (last = total).  CPU only. */
+int32_t dg_query_offsets(const dg_ctx *ctx, int32_t kind, int64_t *offsets);
+
+/* y = H^{Q_k} x (Eq. (1)) for n_vec vectors per element: kinetic term by line
+ * FFTs, local potential, nonlocal projectors.  elem = -1 applies every element
+ * (x_dev, y_dev packed N_k x n_vec per element, concatenated); elem >= 0 applies
+ * element elem only (x_dev, y_dev are N_elem x n_vec).  prec = DG_FP64: double
+ * buffers; DG_FP32: float buffers.  x and y must not overlap.  n_vec must not
+ * exceed J_k + g_k of any element applied.  Errors: DG_ERR_ARG, DG_ERR_HIP. */
+int32_t dg_apply_H(dg_ctx *ctx, int32_t elem, int32_t n_vec, int32_t prec,
+                   const void *x_dev, void *y_dev);
+
+/* Lowest J_k eigenpairs of every H^{Q_k} ("Generating ALB functions";
+ * Algorithm 1 or 2).  eig_dev, resid_dev: J_k FP64 values per element
+ * (DG_OFF_EIG); iters_host: n_elem iteration counts (may be NULL).  The
+ * eigenvectors stay in the context for dg_make_alb / dg_get_vectors.
+ * Returns DG_WARN_NOT_CONVERGED when some element missed tol after max_iter.
+ * Errors: DG_ERR_ARG, DG_ERR_NUMERIC, DG_ERR_HIP. */
+int32_t dg_solve_elements(dg_ctx *ctx, const dg_solve_params *params, double *eig_dev,
+                          double *resid_dev, int32_t *iters_host);
+
+/* Copy the converged eigenvectors (first J_k columns, FP64) to x_dev, packed
+ * N_k x J_k per element (DG_OFF_VEC).  Errors: DG_ERR_STATE before a solve. */
+int32_t dg_get_vectors(dg_ctx *ctx, double *x_dev);
+
+/* ALBs: restrict the J_k eigenvectors to E_k and orthonormalise them there
+ * ("Generating ALB functions": truncated to E_k, orthonormal on E_k).
+ * alb_dev: packed |E_k| x J_k FP64 (DG_OFF_ALB), columns orthonormal, spanning
+ * the restricted eigenvectors; sval_dev: J_k singular values of the
+ * restriction, descending (DG_OFF_EIG).  Errors: DG_ERR_STATE before a solve,
+ * DG_ERR_NUMERIC if the restriction is rank deficient. */
+int32_t dg_make_alb(dg_ctx *ctx, double *alb_dev, double *sval_dev);
+
+/* Band energy E = sum_i f_i psi_i^T H psi_i with Psi = p_m(H) Psi_0, p_m the
+ * degree-m scaled Chebyshev filter of Algorithm 2 / Eq. (8) with bounds
+ * (a, b) and scale a0 per element (bounds_host: 3 values per element), for
+ * n_vec columns per element.  psi0_dev: packed N_k x n_vec (FP64 for DG_FP64,
+ * FP32 for DG_FP32); f_dev: n_vec FP64 weights per element (same for all);
+ * E_dev: one FP64 energy per element.  Intermediates are checkpointed every
+ * ckpt_stride steps for dg_band_energy_backward.  Errors: DG_ERR_ARG. */
+int32_t dg_band_energy(dg_ctx *ctx, int32_t prec, int32_t degree, const double *bounds_host,
+                       int32_t n_vec, const void *psi0_dev, const double *f_dev, double *E_dev);
+
+/* Gradient of the last dg_band_energy call: dpsi0_dev = dE/dPsi_0 (packed
+ * like psi0, scaled by dE_host[k] per element), dv_dev = dE/dV_eff (N_k per
+ * element, DG_OFF_GRID, FP64 or FP32 as psi0).  Recomputes each checkpoint
+ * segment.  Errors: DG_ERR_STATE without a preceding dg_band_energy. */
+int32_t dg_band_energy_backward(dg_ctx *ctx, const double *dE_host, void *dpsi0_dev,
+                                void *dv_dev);
+
+/* Replace V_eff of every element (FP64, DG_OFF_GRID packed), e.g. for an inner
+ * SCF step or for gradients with respect to V.  Errors: DG_ERR_ARG. */
+int32_t dg_set_potential(dg_ctx *ctx, const double *v_dev);
+
+/* Per-kernel-class GPU time accumulated since the last reset, measured with
+ * HIP events on the context's stream.  what: 0 = H*psi kernels, 1 = subspace
+ * GEMMs, 2 = small dense, 3 = other.  ms_host[4], launches_host[4].  reset != 0
+ * clears the counters.  enable != 0 turns timing on (off by default). */
+int32_t dg_timing(dg_ctx *ctx, int32_t enable, int32_t reset, double *ms_host,
+                  int64_t *launches_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_ALB_H */

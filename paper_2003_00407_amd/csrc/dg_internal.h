@@ -1,0 +1,195 @@
+// Internal types shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dg_alb.h"
+
+namespace dg {
+
+constexpr int kMaxBlocks = 8;   // logical N x K blocks per element
+enum BlockId { B_X = 0, B_W = 1, B_P = 2, B_HX = 3, B_HW = 4, B_HP = 5, B_T0 = 6, B_T1 = 7 };
+
+// Per-element data resident on the device (read-only in kernels).
+struct ElemDev {
+  int nx, ny, nz, N;       // Q_k grid
+  int ld;                  // leading dimension of N x K blocks (elements)
+  int K;                   // block width J + guards
+  int J;                   // wanted states
+  int elo[3], en[3];       // E_k box inside Q_k
+  double kx, ky, kz;       // (2 pi / L_axis)^2 / 2: g_axis(f) = k_axis * f^2
+  double vmin;             // min V_eff (preconditioner energy scale)
+  const double* v64;       // V_eff, N values
+  const float* v32;
+  // nonlocal projectors, grouped by shared support (one group per atom)
+  int ngrp, nproj;
+  const int* grp_sptr;     // ngrp+1 offsets into grp_idx
+  const int* grp_pbase;    // ngrp+1: first projector of each group (group g has pbase[g+1]-pbase[g])
+  const int* grp_idx;      // support grid indices
+  const double* grp_val64; // values, for group g projector q: grp_val[vbase + q*len + s]
+  const float* grp_val32;
+  const long long* grp_vbase;  // ngrp offsets into grp_val
+  const double* gamma;     // nproj
+  // transposed projectors over the active grid points (union of supports)
+  int nact;
+  const int* act_idx;      // nact grid indices
+  const int* act_ptr;      // nact+1 offsets into ent_*
+  const int* ent_proj;     // projector ids, ascending per point
+  const double* ent_val64;
+  const float* ent_val32;
+  // per-element block bases (FP64 view; the FP32 view uses the same bytes)
+  void* blk[kMaxBlocks];
+  // per-element small-matrix workspace (FP64)
+  double* small;           // see SmallLayout
+  double* nlc;             // projector overlaps C = B^T X: nproj x Kmax3 (FP64)
+  int kmax3;               // 3 * K
+};
+
+struct SmallLayout {
+  // offsets (doubles) inside ElemDev::small; sizes for K3 = 3K
+  static __host__ __device__ inline long long G(int) { return 0; }
+  static __host__ __device__ inline long long A(int K3) { return (long long)K3 * K3; }
+  static __host__ __device__ inline long long U(int K3) { return 2LL * K3 * K3; }
+  static __host__ __device__ inline long long V(int K3) { return 3LL * K3 * K3; }
+  static __host__ __device__ inline long long C(int K3) { return 4LL * K3 * K3; }
+  static __host__ __device__ inline long long vec(int K3) { return 5LL * K3 * K3; }  // 8 K3-vectors
+  static __host__ __device__ inline long long total(int K3) { return 5LL * K3 * K3 + 8LL * K3 + 64; }
+};
+
+// vec slots inside SmallLayout::vec
+enum VecSlot { VS_THETA = 0, VS_RES = 1, VS_EKIN = 2, VS_D = 3, VS_T0 = 4, VS_T1 = 5, VS_T2 = 6, VS_FLAGS = 7 };
+
+// Shape class: elements with identical grid dims launch together.
+struct ShapeClass {
+  int nx, ny, nz;
+  int nelem;
+  int max_k;
+  int* elem_list_dev;              // nelem element ids
+  std::vector<int> elem_list_host;
+};
+
+struct TimingAcc {
+  double ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  int n_elem = 0;
+  std::vector<ElemDev> elems_host;   // host copy (device pointers inside)
+  ElemDev* elems_dev = nullptr;
+  std::vector<ShapeClass> classes;
+  std::vector<int> J, G, K, N, ld;
+  std::vector<int> elo[3], en[3];
+  std::vector<int64_t> off_x0, off_vec, off_eig, off_alb, off_grid, off_kall;
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  bool solved = false;
+  int solved_K3 = 0;
+  // band-energy state
+  int be_degree = 0, be_prec = 0, be_nvec = 0, be_stride = 1, be_nckpt = 0;
+  std::vector<double> be_bounds;
+  std::vector<double> be_alpha, be_beta, be_c;   // per element coefficient arrays
+  const void* be_psi0 = nullptr;
+  const double* be_f = nullptr;
+  bool be_valid = false;
+  void* ckpt_base = nullptr;       // checkpoint region
+  size_t ckpt_bytes_per_block = 0; // sum over elements of ld*K*8
+  std::vector<int64_t> ckpt_off;   // per element offset (bytes) inside one checkpoint block
+  int max_cheb = 0, ckpt_stride = 1;
+  // timing
+  bool timing = false;
+  TimingAcc tacc;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
+  // misc device scratch
+  int* iota_dev = nullptr;         // 0..n_elem-1
+  int* dev_active = nullptr;       // per element solver flags
+  int* dev_status = nullptr;       // per element RR status
+  int* dev_count = nullptr;        // [active count, NaN count]
+  double* dev_maxres = nullptr;    // per element max residual
+  long long* dev_off_x0 = nullptr; // packed offsets (doubles), per element
+  long long* dev_off_vec = nullptr;
+  long long* dev_off_alb = nullptr;
+  long long* dev_off_grid = nullptr;
+  long long* dev_off_eig = nullptr;
+  std::vector<int> host_ints;      // staging for small async uploads
+  int roles_x = 0;                 // physical block holding the converged X
+  double* gram_part = nullptr;
+  long long gram_part_stride = 0;
+  int gram_part_ld = 0;
+  int gram_max_split = 16;
+  int nl_pending_np = 0, nl_pending_kk = 0;
+  int kmax = 0;                    // max K over elements
+};
+
+// thread-local error message
+void set_error(const std::string& s);
+const char* get_error();
+
+#define DG_HIP(call)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::dg::set_error(std::string(#call " failed: ") + hipGetErrorString(e_));     \
+      return DG_ERR_HIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+// ---- kernel launchers (k_hpsi.hip) ----
+bool grid_supported(int nx, int ny, int nz);
+int launch_hpsi(Ctx& c, int elem, int ncols, int prec, int in_blk, int out_blk, const int* active);
+int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active);
+
+// ---- dense launchers (k_dense.hip) ----
+struct ColSet {
+  int nb;
+  int blk[3];
+};
+enum RRMode { RR_GEN = 0, RR_SVD = 1 };
+struct RotArgs {
+  const ElemDev* elems;
+  const int* active;
+  ColSet S;
+  int kS;              // columns per S block (<= 0: E.K)
+  int nout;            // 1 or 2
+  int out_blk[2];
+  int c0[2], c1[2];    // C row ranges
+  double beta[2];
+  double alpha;
+  long long c_off;     // C matrix offset in E.small (doubles)
+  int c_ld;            // <= 0: ncol
+  int ncol;            // output columns (<= 0: E.K)
+  int c_blockrows;     // if > 0: c0/c1 are in units of S blocks (multiplied by kS)
+  int rows_e;          // 1: the first |E_k| rows only
+};
+int launch_gram(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
+                long long out_off, const int* active);
+int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active);
+int launch_rotate(Ctx& c, int prec, const RotArgs& a);
+int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int* active);
+int launch_check(Ctx& c, int* active, double tol);
+int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
+                     long long out_off, int rows_e);
+int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed);
+int launch_copy_packed(Ctx& c, int prec, int blk, const double* ptr, const long long* off, int ncol,
+                       int to_packed);
+int launch_gather_e(Ctx& c, int src_blk, int dst_blk);
+int launch_copy_rows_out(Ctx& c, int blk, double* out);
+int launch_convert(Ctx& c, int src_blk, int src_prec, int dst_blk, int dst_prec, int ncol);
+int launch_extract_eig(Ctx& c, double* eig, double* resid);
+int launch_extract_theta(Ctx& c, double* out);
+
+// ---- drivers (solver.hip, runtime.hip) ----
+int query_workspace(int n_elem, const dg_element_desc* d, const dg_options* opt, size_t* bytes);
+int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* opt, void* arena,
+           size_t arena_bytes, void* stream);
+int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y);
+int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters);
+int get_vectors(Ctx& c, double* x);
+int make_alb(Ctx& c, double* alb, double* sval);
+
+}  // namespace dg

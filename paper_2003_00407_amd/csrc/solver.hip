@@ -1,0 +1,303 @@
+// Solver drivers: H*psi on caller buffers, LOBPCG (Algorithm 1), Chebyshev-
+// filtered subspace iteration (Algorithm 2 on H^{Q_k}), ALB construction.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+// column-count codes understood by the dense kernels
+constexpr int KC_K = 0;    // E.K
+constexpr int KC_J = -1;   // E.J
+
+// role map: logical block -> physical block
+struct Roles {
+  int r[kMaxBlocks];
+  Roles() {
+    for (int i = 0; i < kMaxBlocks; ++i) r[i] = i;
+  }
+  int operator[](int i) const { return r[i]; }
+};
+
+static int sync_read(Ctx& c, void* dst, const void* src, size_t bytes) {
+  DG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
+  DG_HIP(hipStreamSynchronize(c.stream));
+  return DG_OK;
+}
+
+// Small-matrix offsets differ per element (they scale with the element's own
+// K), so one launch for all elements passes a slot code that each kernel
+// resolves with its element's layout: 0 G, 1 A, 2 U, 3 V, 4 C.
+static long long small_code(int which) { return -1 - which; }
+
+int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y) {
+  if (!x || !y) {
+    set_error("x or y is NULL");
+    return DG_ERR_ARG;
+  }
+  if (elem < -1 || elem >= c.n_elem) {
+    set_error("elem out of range");
+    return DG_ERR_ARG;
+  }
+  if (prec != DG_FP64 && prec != DG_FP32) {
+    set_error("prec must be DG_FP64 or DG_FP32");
+    return DG_ERR_ARG;
+  }
+  for (int e = 0; e < c.n_elem; ++e) {
+    if (elem >= 0 && e != elem) continue;
+    if (n_vec <= 0 || n_vec > c.K[e] + (c.K[e] & 1)) {
+      set_error("n_vec must be in [1, J_k + guards] for every element applied");
+      return DG_ERR_ARG;
+    }
+  }
+  int st;
+  // copy in (packed -> block W), apply W -> HW, copy out
+  if ((st = launch_copy_ext(c, prec, B_W, x, elem, n_vec, 0))) return st;
+  if ((st = launch_hpsi(c, elem, n_vec, prec, B_W, B_HW, nullptr))) return st;
+  if ((st = launch_copy_ext(c, prec, B_HW, y, elem, n_vec, 1))) return st;
+  return DG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// LOBPCG (Algorithm 1) for every element at once
+// ---------------------------------------------------------------------------
+static int rr_and_rotate(Ctx& c, int prec, Roles& R, int nb, const int* active, bool lobpcg) {
+  int st;
+  ColSet S{nb, {R[B_X], R[B_W], R[B_P]}};
+  ColSet HS{nb, {R[B_HX], R[B_HW], R[B_HP]}};
+  if ((st = launch_gram(c, prec, S, KC_K, S, KC_K, small_code(0), active))) return st;
+  if ((st = launch_gram(c, prec, S, KC_K, HS, KC_K, small_code(1), active))) return st;
+  if ((st = launch_rr(c, nb, 0, 0, RR_GEN, active))) return st;
+  // X' = S C (-> T0), P' = [W P] C_WP (-> T1); HX' = HS C, HP' = [HW HP] C_WP
+  RotArgs ra{};
+  ra.active = active;
+  ra.S = S;
+  ra.kS = KC_K;
+  ra.nout = (lobpcg && nb > 1) ? 2 : 1;
+  ra.out_blk[0] = R[B_T0];
+  ra.out_blk[1] = R[B_T1];
+  ra.c0[0] = 0;
+  ra.c1[0] = nb;
+  ra.c0[1] = 1;
+  ra.c1[1] = nb;
+  ra.beta[0] = ra.beta[1] = 0.0;
+  ra.alpha = 1.0;
+  ra.c_off = small_code(4);
+  ra.c_ld = 0;
+  ra.ncol = KC_K;
+  ra.c_blockrows = 1;
+  if ((st = launch_rotate(c, prec, ra))) return st;
+  // X, P are free now: write HX', HP' there
+  ra.S = HS;
+  ra.out_blk[0] = R[B_X];
+  ra.out_blk[1] = R[B_P];
+  if ((st = launch_rotate(c, prec, ra))) return st;
+  Roles n = R;
+  n.r[B_X] = R[B_T0];
+  n.r[B_P] = R[B_T1];
+  n.r[B_HX] = R[B_X];
+  n.r[B_HP] = R[B_P];
+  n.r[B_T0] = R[B_HX];
+  n.r[B_T1] = R[B_HP];
+  R = n;
+  return DG_OK;
+}
+
+static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int* iters, int* n_done) {
+  int st;
+  int* active = c.dev_active;
+  // start: H X, then Rayleigh-Ritz on span(X) (orthonormalises X, step 1)
+  {
+    std::vector<int> ones(c.n_elem, 1);
+    c.host_ints = ones;
+    DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
+  }
+  if ((st = launch_hpsi(c, -1, 0, prec, R[B_X], R[B_HX], active))) return st;
+  if ((st = rr_and_rotate(c, prec, R, 1, active, false))) return st;
+  bool have_p = false;
+  std::vector<int> it_elem(c.n_elem, 0);
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    if ((st = launch_residual(c, prec, R[B_X], R[B_HX], 0, active))) return st;
+    if ((st = launch_check(c, active, tol))) return st;
+    int cnt[2];
+    if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
+    if (cnt[1] > 0) {
+      set_error("non-finite residual in " + std::to_string(cnt[1]) + " element(s)");
+      return DG_ERR_NUMERIC;
+    }
+    {
+      std::vector<int> act(c.n_elem);
+      if ((st = sync_read(c, act.data(), active, sizeof(int) * c.n_elem))) return st;
+      for (int e = 0; e < c.n_elem; ++e)
+        if (act[e] > 0) it_elem[e] = it;
+    }
+    if (cnt[0] == 0) break;
+    // W = T(HX - X Theta)  (Eq. (3), step 3)
+    if ((st = launch_teter(c, prec, R[B_X], R[B_HX], R[B_W], 0, active))) return st;
+    // W <- W - X (X^T W)
+    {
+      ColSet SX{1, {R[B_X], 0, 0}}, SW{1, {R[B_W], 0, 0}};
+      if ((st = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active))) return st;
+      RotArgs ra{};
+      ra.active = active;
+      ra.S = SX;
+      ra.kS = KC_K;
+      ra.nout = 1;
+      ra.out_blk[0] = R[B_W];
+      ra.c0[0] = 0;
+      ra.c1[0] = 1;
+      ra.beta[0] = 1.0;
+      ra.alpha = -1.0;
+      ra.c_off = small_code(2);
+      ra.ncol = KC_K;
+      ra.c_blockrows = 1;
+      if ((st = launch_rotate(c, prec, ra))) return st;
+    }
+    // H W
+    if ((st = launch_hpsi(c, -1, 0, prec, R[B_W], R[B_HW], active))) return st;
+    // S = [X, W, P], projected problem (Eq. (4)), rotations (Eq. (2))
+    if ((st = rr_and_rotate(c, prec, R, have_p ? 3 : 2, active, true))) return st;
+    have_p = true;
+  }
+  // final residuals for reporting (every element)
+  {
+    std::vector<int> ones(c.n_elem, 1);
+    c.host_ints = ones;
+    DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
+  }
+  if ((st = launch_residual(c, prec, R[B_X], R[B_HX], 0, active))) return st;
+  if ((st = launch_check(c, active, tol))) return st;
+  int cnt[2];
+  if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
+  if (iters)
+    for (int e = 0; e < c.n_elem; ++e) iters[e] = it_elem[e];
+  *n_done = c.n_elem - cnt[0];
+  return cnt[1] > 0 ? DG_ERR_NUMERIC : DG_OK;
+}
+
+int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, Roles& R, int* iters, int* n_done);
+
+int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters) {
+  if (!p || !eig || !resid) {
+    set_error("params, eig_dev and resid_dev must be non-NULL");
+    return DG_ERR_ARG;
+  }
+  if (!p->x0_dev) {
+    set_error("x0_dev is required (seeded initial blocks)");
+    return DG_ERR_ARG;
+  }
+  if (p->method != DG_LOBPCG && p->method != DG_CHFSI) {
+    set_error("unknown method");
+    return DG_ERR_ARG;
+  }
+  if (p->precision != DG_FP64 && p->precision != DG_MIXED) {
+    set_error("precision must be DG_FP64 or DG_MIXED");
+    return DG_ERR_ARG;
+  }
+  if (!(p->tol > 0.0) || p->max_iter <= 0) {
+    set_error("tol must be > 0 and max_iter > 0");
+    return DG_ERR_ARG;
+  }
+  int st;
+  Roles R;
+  std::vector<int> it1(c.n_elem, 0), it2(c.n_elem, 0);
+  int done = 0;
+  if (p->precision == DG_FP64) {
+    if ((st = launch_copy_packed(c, DG_FP64, R[B_X], p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
+    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP64, p->tol, p->max_iter, R, it1.data(), &done)
+                                : run_chfsi(c, DG_FP64, p->tol, p->max_iter, p->cheb_degree, R, it1.data(), &done);
+    if (st < 0) return st;
+  } else {
+    const double tmp = p->tol_mixed > 0.0 ? p->tol_mixed : 1e-4;
+    if ((st = launch_copy_packed(c, DG_FP32, R[B_X], p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
+    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, R, it1.data(), &done)
+                                : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree, R,
+                                            it1.data(), &done);
+    if (st < 0) return st;
+    // promote X to FP64 (into W's storage), then FP64 refinement sweeps
+    if ((st = launch_convert(c, R[B_X], DG_FP32, R[B_W], DG_FP64, KC_K))) return st;
+    std::swap(R.r[B_X], R.r[B_W]);
+    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, R, it2.data(), &done);
+    if (st < 0) return st;
+  }
+  c.roles_x = R[B_X];
+  c.solved = true;
+  // outputs: theta, residuals of the J wanted states
+  if ((st = launch_extract_eig(c, eig, resid))) return st;
+  if (iters)
+    for (int e = 0; e < c.n_elem; ++e) iters[e] = it1[e] + it2[e];
+  DG_HIP(hipStreamSynchronize(c.stream));
+  return done == c.n_elem ? DG_OK : DG_WARN_NOT_CONVERGED;
+}
+
+int get_vectors(Ctx& c, double* x) {
+  if (!c.solved) {
+    set_error("no solve has completed on this context");
+    return DG_ERR_STATE;
+  }
+  if (!x) {
+    set_error("x_dev is NULL");
+    return DG_ERR_ARG;
+  }
+  return launch_copy_packed(c, DG_FP64, c.roles_x, x, c.dev_off_vec, KC_J, 1);
+}
+
+// ALB: gather E_k rows, SVD by eigen-decomposition of the Gram (twice)
+int make_alb(Ctx& c, double* alb, double* sval) {
+  if (!c.solved) {
+    set_error("no solve has completed on this context");
+    return DG_ERR_STATE;
+  }
+  if (!alb || !sval) {
+    set_error("alb_dev and sval_dev must be non-NULL");
+    return DG_ERR_ARG;
+  }
+  int st;
+  const int X = c.roles_x;
+  // physical blocks other than X for scratch
+  int t0 = (X == B_T0) ? B_W : B_T0;
+  int t1 = (X == B_T1) ? B_P : B_T1;
+  if (t1 == t0) t1 = B_HW;
+  if ((st = launch_gather_e(c, X, t0))) return st;
+  ColSet S0{1, {t0, 0, 0}}, S1{1, {t1, 0, 0}};
+  if ((st = launch_gram_rows(c, DG_FP64, S0, KC_J, S0, KC_J, small_code(0), 1))) return st;
+  if ((st = launch_rr(c, 0, KC_J, KC_J, RR_SVD, nullptr))) return st;
+  if ((st = launch_extract_theta(c, sval))) return st;
+  RotArgs ra{};
+  ra.S = S0;
+  ra.kS = KC_J;
+  ra.nout = 1;
+  ra.out_blk[0] = t1;
+  ra.c0[0] = 0;
+  ra.c1[0] = 1;
+  ra.alpha = 1.0;
+  ra.c_off = small_code(4);
+  ra.ncol = KC_J;
+  ra.c_blockrows = 1;
+  ra.rows_e = 1;
+  if ((st = launch_rotate(c, DG_FP64, ra))) return st;
+  // second pass restores orthonormality to working precision
+  if ((st = launch_gram_rows(c, DG_FP64, S1, KC_J, S1, KC_J, small_code(0), 1))) return st;
+  if ((st = launch_rr(c, 0, KC_J, KC_J, RR_SVD, nullptr))) return st;
+  ra.S = S1;
+  ra.out_blk[0] = t0;
+  if ((st = launch_rotate(c, DG_FP64, ra))) return st;
+  if ((st = launch_copy_rows_out(c, t0, alb))) return st;
+  DG_HIP(hipStreamSynchronize(c.stream));
+  return DG_OK;
+}
+
+}  // namespace dg
+
+namespace dg {
+int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, Roles& R, int* iters, int* n_done) {
+  (void)c; (void)prec; (void)tol; (void)max_iter; (void)degree; (void)R; (void)iters; (void)n_done;
+  set_error("Chebyshev-filtered solver not available in this build");
+  return DG_ERR_ARG;
+}
+}  // namespace dg

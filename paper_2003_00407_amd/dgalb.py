@@ -1,0 +1,236 @@
+"""ctypes binding of the C ABI in include/dg_alb.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libdgalb.so``; PyTorch provides
+device memory (the arena and the caller buffers) and the HIP stream.  If the
+library has not been built, importing this module raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgalb.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2003_00407_amd/build.py "
+                      "(or __graft_entry__.build())")
+_lib = C.CDLL(LIB_PATH)
+
+DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
+DG_ERR_ARG, DG_ERR_SHAPE, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_NUMERIC, DG_ERR_STATE = -1, -2, -3, -4, -5, -6
+DG_FP64, DG_MIXED, DG_FP32 = 0, 1, 2
+DG_LOBPCG, DG_CHFSI = 0, 1
+DG_OFF_X0, DG_OFF_VEC, DG_OFF_EIG, DG_OFF_ALB, DG_OFF_GRID, DG_OFF_KALL = range(6)
+
+EXPORTED = [
+    "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
+    "dg_query_offsets", "dg_apply_H", "dg_solve_elements", "dg_get_vectors", "dg_make_alb",
+    "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing",
+]
+
+
+class ElementDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3), ("len", C.c_double * 3), ("elem_lo", C.c_int32 * 3),
+        ("elem_n", C.c_int32 * 3), ("n_states", C.c_int32), ("v_eff", C.POINTER(C.c_double)),
+        ("n_proj", C.c_int32), ("proj_ptr", C.POINTER(C.c_int64)), ("proj_idx", C.POINTER(C.c_int32)),
+        ("proj_val", C.POINTER(C.c_double)), ("gamma", C.POINTER(C.c_double)),
+    ]
+
+
+class Options(C.Structure):
+    _fields_ = [("n_guard", C.c_int32), ("max_cheb_degree", C.c_int32), ("ckpt_stride", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
+                ("tol_mixed", C.c_double), ("max_iter", C.c_int32), ("cheb_degree", C.c_int32),
+                ("x0_dev", C.c_void_p)]
+
+
+_lib.dg_status_string.restype = C.c_char_p
+_lib.dg_status_string.argtypes = [C.c_int32]
+_lib.dg_last_error.restype = C.c_char_p
+_lib.dg_last_error.argtypes = [C.c_void_p]
+_lib.dg_query_workspace.argtypes = [C.c_int32, C.POINTER(ElementDesc), C.POINTER(Options), C.POINTER(C.c_size_t)]
+_lib.dg_create_elements.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ElementDesc), C.POINTER(Options),
+                                    C.c_void_p, C.c_size_t, C.c_void_p]
+_lib.dg_destroy.argtypes = [C.c_void_p]
+_lib.dg_destroy.restype = None
+_lib.dg_query_offsets.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
+_lib.dg_apply_H.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+_lib.dg_solve_elements.argtypes = [C.c_void_p, C.POINTER(SolveParams), C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_int32)]
+_lib.dg_get_vectors.argtypes = [C.c_void_p, C.c_void_p]
+_lib.dg_make_alb.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.dg_band_energy.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.dg_band_energy_backward.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
+_lib.dg_set_potential.argtypes = [C.c_void_p, C.c_void_p]
+_lib.dg_timing.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+
+
+class DGError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.dg_last_error(None).decode(errors="replace")
+        super().__init__(f"{where}: {_lib.dg_status_string(status).decode()} ({msg})")
+
+
+def _check(st: int, where: str) -> int:
+    if st < 0:
+        raise DGError(st, where)
+    return st
+
+
+def status_string(st: int) -> str:
+    return _lib.dg_status_string(st).decode()
+
+
+def last_error() -> str:
+    return _lib.dg_last_error(None).decode(errors="replace")
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class HostDescs:
+    """ctypes descriptors for a list of workloads.Element (keeps the arrays alive)."""
+
+    def __init__(self, elements: Sequence):
+        self.keep: List[np.ndarray] = []
+        arr = (ElementDesc * len(elements))()
+        for i, el in enumerate(elements):
+            d = arr[i]
+            d.n[:] = list(el.n)
+            d.len[:] = list(el.length)
+            d.elem_lo[:] = list(el.elem_lo)
+            d.elem_n[:] = list(el.elem_n)
+            d.n_states = int(el.n_states)
+            v = np.ascontiguousarray(el.v_eff, dtype=np.float64)
+            pp = np.ascontiguousarray(el.proj_ptr, dtype=np.int64)
+            pi = np.ascontiguousarray(el.proj_idx, dtype=np.int32)
+            pv = np.ascontiguousarray(el.proj_val, dtype=np.float64)
+            g = np.ascontiguousarray(el.gamma, dtype=np.float64)
+            self.keep += [v, pp, pi, pv, g]
+            d.v_eff = _ptr(v, C.c_double)
+            d.n_proj = int(g.size)
+            d.proj_ptr = _ptr(pp, C.c_int64)
+            d.proj_idx = _ptr(pi, C.c_int32)
+            d.proj_val = _ptr(pv, C.c_double)
+            d.gamma = _ptr(g, C.c_double)
+        self.arr = arr
+        self.n = len(elements)
+
+
+def query_workspace(elements: Sequence, n_guard: int = -1, max_cheb_degree: int = 0,
+                    ckpt_stride: int = 1) -> int:
+    """Arena bytes for these elements (CPU only, never touches the GPU)."""
+    hd = HostDescs(elements)
+    opt = Options(n_guard, max_cheb_degree, ckpt_stride, 0)
+    out = C.c_size_t(0)
+    _check(_lib.dg_query_workspace(hd.n, hd.arr, C.byref(opt), C.byref(out)), "dg_query_workspace")
+    return int(out.value)
+
+
+class Elements:
+    """A batch of extended elements resident on one GPU (the dg_ctx)."""
+
+    def __init__(self, elements: Sequence, n_guard: int = -1, max_cheb_degree: int = 0,
+                 ckpt_stride: int = 1, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.elements = list(elements)
+        self.hd = HostDescs(self.elements)
+        self.opt = Options(n_guard, max_cheb_degree, ckpt_stride, 0)
+        nbytes = C.c_size_t(0)
+        _check(_lib.dg_query_workspace(self.hd.n, self.hd.arr, C.byref(self.opt), C.byref(nbytes)),
+               "dg_query_workspace")
+        self.arena = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.arena.data_ptr()
+        self._arena_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p(0)
+        _check(_lib.dg_create_elements(C.byref(self.ctx), self.hd.n, self.hd.arr, C.byref(self.opt),
+                                       C.c_void_p(self._arena_ptr), C.c_size_t(int(nbytes.value)),
+                                       C.c_void_p(self.stream.cuda_stream)), "dg_create_elements")
+        self.n_elem = self.hd.n
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            _lib.dg_destroy(ctx)
+            self.ctx = C.c_void_p(0)
+
+    # ---- layout helpers
+    def offsets(self, kind: int) -> np.ndarray:
+        out = np.zeros(self.n_elem + 1, dtype=np.int64)
+        _check(_lib.dg_query_offsets(self.ctx, kind, _ptr(out, C.c_int64)), "dg_query_offsets")
+        return out
+
+    def _dev(self, n, dtype):
+        return self.torch.empty(int(n), dtype=dtype, device=self.device)
+
+    # ---- entry points
+    def apply_H(self, x, n_vec: int, prec: int = DG_FP64, elem: int = -1):
+        """y = H x for packed x (N_k x n_vec per element, column-major)."""
+        torch = self.torch
+        dt = torch.float64 if prec == DG_FP64 else torch.float32
+        if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous CUDA tensor of the precision's dtype")
+        y = torch.empty_like(x)
+        _check(_lib.dg_apply_H(self.ctx, elem, n_vec, prec, C.c_void_p(x.data_ptr()),
+                               C.c_void_p(y.data_ptr())), "dg_apply_H")
+        return y
+
+    def solve(self, x0, method: int = DG_LOBPCG, precision: int = DG_FP64, tol: float = 1e-8,
+              tol_mixed: float = 1e-4, max_iter: int = 300, cheb_degree: int = 16):
+        """Lowest J_k eigenpairs of every element; returns (eig, resid, iters, status)."""
+        torch = self.torch
+        if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
+            raise ValueError("x0 must be a contiguous CUDA float64 tensor (packed N_k x (J_k+g_k))")
+        n_eig = int(self.offsets(DG_OFF_EIG)[-1])
+        eig = self._dev(n_eig, torch.float64)
+        res = self._dev(n_eig, torch.float64)
+        iters = (C.c_int32 * self.n_elem)()
+        p = SolveParams(method, precision, tol, tol_mixed, max_iter, cheb_degree, C.c_void_p(x0.data_ptr()))
+        st = _check(_lib.dg_solve_elements(self.ctx, C.byref(p), C.c_void_p(eig.data_ptr()),
+                                           C.c_void_p(res.data_ptr()), iters), "dg_solve_elements")
+        return eig, res, np.array(list(iters), dtype=np.int32), st
+
+    def vectors(self):
+        n = int(self.offsets(DG_OFF_VEC)[-1])
+        out = self._dev(n, self.torch.float64)
+        _check(_lib.dg_get_vectors(self.ctx, C.c_void_p(out.data_ptr())), "dg_get_vectors")
+        return out
+
+    def make_alb(self):
+        torch = self.torch
+        alb = self._dev(int(self.offsets(DG_OFF_ALB)[-1]), torch.float64)
+        sv = self._dev(int(self.offsets(DG_OFF_EIG)[-1]), torch.float64)
+        _check(_lib.dg_make_alb(self.ctx, C.c_void_p(alb.data_ptr()), C.c_void_p(sv.data_ptr())),
+               "dg_make_alb")
+        return alb, sv
+
+    def timing(self, enable: bool = True, reset: bool = False):
+        ms = (C.c_double * 4)()
+        n = (C.c_int64 * 4)()
+        _check(_lib.dg_timing(self.ctx, int(enable), int(reset), ms, n), "dg_timing")
+        return list(ms), list(n)
+
+
+def pack_initial(elements: Sequence, seed_base: int, n_guard: int = -1):
+    """Seeded initial blocks, packed N_k x (J_k + g_k) per element (host float64)."""
+    import workloads as W
+    parts = []
+    for k, el in enumerate(elements):
+        g = W.guard_count(el.n_states) if n_guard < 0 else n_guard
+        parts.append(W.initial_block(el.npts, el.n_states + g, seed=seed_base + k).ravel())
+    return np.concatenate(parts)

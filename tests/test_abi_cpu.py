@@ -1,0 +1,90 @@
+"""C-ABI library: loads without a GPU, exports every declared symbol, validates arguments."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2003_00407_amd import dgalb
+    return dgalb
+
+
+def test_header_symbols_exported():
+    hdr = open(os.path.join(ROOT, "include", "dg_alb.h")).read()
+    declared = set(re.findall(r"\b(dg_[a-z_A-Z]+)\s*\(", hdr))
+    d = _lib()
+    lib = ctypes.CDLL(d.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in dg_alb.h but not exported"
+    assert declared == set(d.EXPORTED)
+
+
+def test_status_strings():
+    d = _lib()
+    assert d.status_string(0) == "DG_OK"
+    assert d.status_string(-2) == "DG_ERR_SHAPE"
+    assert d.status_string(99) == "DG_UNKNOWN_STATUS"
+
+
+def test_query_workspace_sizes():
+    d = _lib()
+    els = W.make_config("c1").elements
+    b1 = d.query_workspace(els)
+    assert b1 > 8 * 16 ** 3 * 12 * 8  # eight N x K FP64 blocks at least
+    b2 = d.query_workspace(W.small_slab())
+    assert b2 > b1
+
+
+def test_query_workspace_rejects_bad_input():
+    d = _lib()
+    el = W.make_config("c1").elements[0]
+    import dataclasses
+    bad = dataclasses.replace(el, n=(16, 16, 20))          # 20 not a supported line length
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([bad])
+    assert e.value.status == d.DG_ERR_SHAPE
+    bad = dataclasses.replace(el, elem_lo=(10, 0, 0), elem_n=(10, 16, 16))
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([bad])
+    assert e.value.status == d.DG_ERR_ARG
+    bad = dataclasses.replace(el, n_states=0)
+    with pytest.raises(d.DGError):
+        d.query_workspace([bad])
+    bad = dataclasses.replace(el, n_states=85)              # J + guards > 88
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([bad])
+    assert e.value.status == d.DG_ERR_SHAPE
+    # projector indices must be ascending
+    sl = W.small_slab()[0]
+    idx = sl.proj_idx.copy()
+    idx[1], idx[2] = idx[2], idx[1]
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([dataclasses.replace(sl, proj_idx=idx)])
+    assert e.value.status == d.DG_ERR_ARG
+    assert "ascending" in d.last_error()
+
+
+def test_null_context_calls_fail_cleanly():
+    d = _lib()
+    lib = d._lib
+    assert lib.dg_apply_H(None, -1, 1, 0, None, None) == d.DG_ERR_ARG
+    assert lib.dg_solve_elements(None, None, None, None, None) == d.DG_ERR_ARG
+    assert lib.dg_make_alb(None, None, None) == d.DG_ERR_ARG
+    assert lib.dg_get_vectors(None, None) == d.DG_ERR_ARG
+    lib.dg_destroy(None)
+
+
+def test_pack_initial_layout():
+    d = _lib()
+    els = W.small_slab()[:2]
+    x0 = d.pack_initial(els, 10)
+    g = W.guard_count(els[0].n_states)
+    assert x0.size == sum(e.npts * (e.n_states + g) for e in els)
+    assert np.array_equal(x0[: els[0].npts], W.initial_block(els[0].npts, els[0].n_states + g, 10)[0])

@@ -1,0 +1,80 @@
+"""Eigen-solves and ALBs on the GPU against the oracle (eigenvalues <= 1e-8 Ha)."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads as W
+from oracle import alb as oalb
+from oracle import lobpcg as olobpcg
+from oracle import planewave
+from tests.gpu_util import need_torch_cuda, unpack
+
+pytestmark = pytest.mark.gpu
+
+EIG_TOL = 1e-8
+
+
+def _solve(els, method=0, precision=0, tol=1e-9, seed_base=100, max_iter=300):
+    torch = need_torch_cuda()
+    from paper_2003_00407_amd import dgalb as D
+    print(f"[solve] n_elem={len(els)} grid={els[0].n} J={els[0].n_states} method={method} "
+          f"prec={precision}", flush=True)
+    E = D.Elements(els)
+    x0 = torch.tensor(D.pack_initial(els, seed_base), dtype=torch.float64, device="cuda")
+    eig, res, iters, st = E.solve(x0, method=method, precision=precision, tol=tol, max_iter=max_iter)
+    torch.cuda.synchronize()
+    off = E.offsets(D.DG_OFF_EIG)
+    eig = eig.cpu().numpy()
+    res = res.cpu().numpy()
+    return E, [eig[off[k]:off[k + 1]] for k in range(len(els))], \
+        [res[off[k]:off[k + 1]] for k in range(len(els))], iters, st
+
+
+def test_c1_lobpcg_vs_dense():
+    el = W.make_config("c1").elements[0]
+    E, eig, res, iters, st = _solve([el])
+    H = planewave.dense_H(el, kinetic=None) if el.npts <= 2000 else None
+    # dense reference from the explicit separable-circulant kinetic matrix (pinned in test_oracle)
+    from tests.test_oracle import _separable_dense_T
+    Hd = _separable_dense_T(el.n, el.length) + np.diag(el.v_eff)
+    ev = scipy.linalg.eigh(Hd, eigvals_only=True, subset_by_index=[0, 7])
+    print("iters", iters, "max res", res[0].max(), "err", np.abs(eig[0] - ev).max())
+    assert st == 0
+    assert np.max(np.abs(eig[0] - ev)) < EIG_TOL
+    assert res[0].max() <= 1e-9
+
+
+def test_slab_lobpcg_vs_oracle_and_alb():
+    torch = need_torch_cuda()
+    from paper_2003_00407_amd import dgalb as D
+    els = W.small_slab(n_states=8)
+    E, eig, res, iters, st = _solve(els)
+    assert st == 0
+    X = unpack(E.vectors().cpu().numpy(), E.offsets(D.DG_OFF_VEC), [e.npts for e in els],
+               [e.n_states for e in els])
+    alb, sv = E.make_alb()
+    A = unpack(alb.cpu().numpy(), E.offsets(D.DG_OFF_ALB), [int(np.prod(e.elem_n)) for e in els],
+               [e.n_states for e in els])
+    offe = E.offsets(D.DG_OFF_EIG)
+    sv = sv.cpu().numpy()
+    for k, el in enumerate(els):
+        J = el.n_states
+        ref = olobpcg.lobpcg(el, W.initial_block(el.npts, J + 4, 7000 + k).T, J, tol=1e-10)
+        err = np.max(np.abs(eig[k] - ref.eigvals[:J]))
+        gap = ref.eigvals[J] - ref.eigvals[J - 1]
+        print(f"elem {k}: iters {iters[k]} eig err {err:.2e} gap {gap:.3e} res {res[k].max():.2e}")
+        assert err < EIG_TOL
+        # orthonormal eigenvectors with small residuals (certificate with the oracle's H)
+        Xk = X[k]
+        assert np.max(np.abs(Xk.T @ Xk - np.eye(J))) < 1e-10
+        R = planewave.hpsi(el, Xk) - Xk * eig[k][None, :]
+        assert np.linalg.norm(R, axis=0).max() < 1e-8
+        # ALBs: orthonormal on E_k, span of the restricted eigenvectors, oracle's singular values
+        U_ref, s_ref = oalb.make_alb(el, ref.X, J)
+        Ak = A[k]
+        assert np.max(np.abs(Ak.T @ Ak - np.eye(J))) < 1e-12
+        phi = oalb.restrict(el, Xk)
+        assert np.linalg.norm(phi - Ak @ (Ak.T @ phi), 2) < 1e-11
+        if gap > 1e-2:
+            assert oalb.max_principal_angle(U_ref, Ak) < 1e-6
+            assert np.max(np.abs(sv[offe[k]:offe[k + 1]] - s_ref)) < 1e-7
