@@ -124,6 +124,7 @@ struct Ctx {
   int gram_max_split = 16;
   int nl_pending_np = 0, nl_pending_kk = 0;
   int kmax = 0;                    // max K over elements
+  int log_level = 0;               // DG_LOG environment variable
 };
 
 // thread-local error message
@@ -182,6 +183,7 @@ int launch_copy_rows_out(Ctx& c, int blk, double* out);
 int launch_convert(Ctx& c, int src_blk, int src_prec, int dst_blk, int dst_prec, int ncol);
 int launch_extract_eig(Ctx& c, double* eig, double* resid);
 int launch_extract_theta(Ctx& c, double* out);
+int launch_permute(Ctx& c, const int* perm, const int* active);
 
 // ---- drivers (solver.hip, runtime.hip) ----
 int query_workspace(int n_elem, const dg_element_desc* d, const dg_options* opt, size_t* bytes);

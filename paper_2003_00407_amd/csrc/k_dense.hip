@@ -237,58 +237,69 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
   __shared__ double sh[16];
   __shared__ int brk;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // inputs: G (n x n, ld n) and A (n x n, ld n) as written by the Gram reduction
-  // move them to ld = np with a zero pad row/column
-  if (tid == 0) brk = 0;
-  for (int idx = tid; idx < np * np; idx += nt) {
-    const int i = idx / np, j = idx % np;
-    Um[idx] = (i < n && j < n) ? G[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
-    Vm[idx] = (i < n && j < n) ? Am[(size_t)i * n + j] : 0.0;
-  }
-  __syncthreads();
+  // Inputs: G and A (n x n, ld n) as written by the Gram reduction.  For the
+  // generalised problem the leading blocks of S are tried in turn when the
+  // overlap Cholesky breaks down: [X W P], then [X W], then [X]; the
+  // coefficients of dropped blocks are zero (restart without P).
+  int n_cur = n;
   if (A.mode == RR_GEN) {
-    // scaling d_i = G_ii^{-1/2}
-    for (int i = tid; i < np; i += nt) {
-      const double gii = Um[(size_t)i * np + i];
-      if (!(gii > 0.0)) brk = 1;
-      d[i] = (i < n && gii > 0.0) ? 1.0 / sqrt(gii) : 1.0;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      Um[idx] *= d[i] * d[j];
-      const double a = 0.5 * (Vm[idx] + Vm[(size_t)j * np + i]);
-      Am[idx] = a * d[i] * d[j];
-    }
-    __syncthreads();
-    // Cholesky (upper, in place in Um): Um = U^T U
-    for (int j = 0; j < n; ++j) {
-      const double piv = Um[(size_t)j * np + j];
-      if (!(piv > 1e-13)) {
-        if (tid == 0) brk = 1;
-      }
-      const double ujj = sqrt(fmax(piv, 1e-300));
+    int attempt = 0;
+    for (;;) {
+      const int m = n_cur;
+      if (tid == 0) brk = 0;
       __syncthreads();
-      for (int k = j + 1 + tid; k < n; k += nt) Um[(size_t)j * np + k] /= ujj;
-      __syncthreads();
-      if (tid == 0) Um[(size_t)j * np + j] = ujj;
-      const int m = n - j - 1;
-      for (int idx = tid; idx < m * m; idx += nt) {
-        const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-        if (k >= i) Um[(size_t)i * np + k] -= Um[(size_t)j * np + i] * Um[(size_t)j * np + k];
+      for (int idx = tid; idx < np * np; idx += nt) {
+        const int i = idx / np, j = idx % np;
+        const bool in = (i < m && j < m);
+        Um[idx] = in ? G[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
+        Vm[idx] = in ? 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]) : 0.0;
       }
       __syncthreads();
+      for (int i = tid; i < np; i += nt) {
+        const double gii = Um[(size_t)i * np + i];
+        if (!(gii > 0.0)) brk = 1;
+        d[i] = (i < m && gii > 0.0) ? 1.0 / sqrt(gii) : (i < m ? 0.0 : 1.0);
+      }
+      __syncthreads();
+      for (int idx = tid; idx < np * np; idx += nt) {
+        const int i = idx / np, j = idx % np;
+        Um[idx] *= d[i] * d[j];
+        Vm[idx] *= d[i] * d[j];
+      }
+      __syncthreads();
+      // Cholesky (upper, in place in Um): Um = U^T U
+      for (int j = 0; j < m; ++j) {
+        const double piv = Um[(size_t)j * np + j];
+        if (!(piv > 1e-13) && tid == 0) brk = 1;
+        const double ujj = sqrt(fmax(piv, 1e-300));
+        __syncthreads();
+        for (int k = j + 1 + tid; k < m; k += nt) Um[(size_t)j * np + k] /= ujj;
+        __syncthreads();
+        if (tid == 0) Um[(size_t)j * np + j] = ujj;
+        const int mm = m - j - 1;
+        for (int idx = tid; idx < mm * mm; idx += nt) {
+          const int i = j + 1 + idx / mm, k = j + 1 + idx % mm;
+          if (k >= i) Um[(size_t)i * np + k] -= Um[(size_t)j * np + i] * Um[(size_t)j * np + k];
+        }
+        __syncthreads();
+      }
+      if (!brk) break;
+      ++attempt;
+      if (n_cur > K) {
+        n_cur -= K;
+      } else {
+        if (tid == 0) A.status[e] = 2;
+        return;   // unrecoverable: C is left as is and the status reports it
+      }
+      __syncthreads();
     }
+    if (tid == 0) A.status[e] = attempt;
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
       if (j < i) Um[idx] = 0.0;
     }
     __syncthreads();
-    if (brk) {
-      if (tid == 0) A.status[e] = 1;
-      return;
-    }
-    // Z = U^{-1} (upper), column j by back substitution, into G
+    // Z = U^{-1} (upper), column j by back substitution, into G (inputs are no longer needed)
     for (int j = tid; j < np; j += nt) {
       for (int i = np - 1; i >= 0; --i) {
         double s = (i == j) ? 1.0 : 0.0;
@@ -297,32 +308,33 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
       }
     }
     __syncthreads();
-    // Vm = A Z ; Am = Z^T Vm  (standard problem)
+    // Am = A' Z ; Um = Z^T Am ; Am = sym(Um)  (standard problem)
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
       double s = 0.0;
-      for (int k = 0; k <= j; ++k) s += Am[(size_t)i * np + k] * G[(size_t)k * np + j];
-      Vm[idx] = s;
+      for (int k = 0; k <= j; ++k) s += Vm[(size_t)i * np + k] * G[(size_t)k * np + j];
+      Am[idx] = s;
     }
     __syncthreads();
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
       double s = 0.0;
-      for (int k = 0; k <= i; ++k) s += G[(size_t)k * np + i] * Vm[(size_t)k * np + j];
+      for (int k = 0; k <= i; ++k) s += G[(size_t)k * np + i] * Am[(size_t)k * np + j];
       Um[idx] = s;
     }
     __syncthreads();
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
-      Am[idx] = (i < n && j < n) ? 0.5 * (Um[idx] + Um[(size_t)j * np + i]) : 0.0;
+      Am[idx] = (i < n_cur && j < n_cur) ? 0.5 * (Um[idx] + Um[(size_t)j * np + i]) : 0.0;
     }
   } else {
     // RR_SVD: eigen-decomposition of the Gram matrix itself
-    for (int idx = tid; idx < np * np; idx += nt) Am[idx] = Um[idx];
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
-      if (i >= n || j >= n) Am[idx] = 0.0;
+      Um[idx] = (i < n && j < n) ? G[(size_t)i * n + j] : 0.0;
     }
+    __syncthreads();
+    for (int idx = tid; idx < np * np; idx += nt) Am[idx] = Um[idx];
   }
   __syncthreads();
   // ---- cyclic Jacobi, round-robin pairs, V accumulated in Vm
@@ -408,12 +420,12 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     }
   }
   // eigenvalues on the diagonal; rank them (ascending for RR_GEN, descending for RR_SVD)
-  for (int i = tid; i < np; i += nt) lam[i] = (i < n) ? Am[(size_t)i * np + i] : 0.0;
+  for (int i = tid; i < np; i += nt) lam[i] = (i < n_cur) ? Am[(size_t)i * np + i] : 0.0;
   __syncthreads();
   int* rank_of = reinterpret_cast<int*>(csv);   // reuse: position -> original index
-  for (int i = tid; i < n; i += nt) {
+  for (int i = tid; i < n_cur; i += nt) {
     int rk = 0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = 0; j < n_cur; ++j) {
       const bool before = (A.mode == RR_GEN) ? (lam[j] < lam[i] || (lam[j] == lam[i] && j < i))
                                              : (lam[j] > lam[i] || (lam[j] == lam[i] && j < i));
       rk += before;
@@ -426,9 +438,13 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     // C = D Z V[:, sel]  (n x nkeep, ld nkeep)
     for (int idx = tid; idx < n * nkeep; idx += nt) {
       const int i = idx / nkeep, j = idx % nkeep;
+      if (i >= n_cur) {
+        Cm[(size_t)i * nkeep + j] = 0.0;
+        continue;
+      }
       const int col = rank_of[j];
       double s = 0.0;
-      for (int k = i; k < n; ++k) s += G[(size_t)i * np + k] * Vm[(size_t)k * np + col];
+      for (int k = i; k < n_cur; ++k) s += G[(size_t)i * np + k] * Vm[(size_t)k * np + col];
       Cm[(size_t)i * nkeep + j] = d[i] * s;
     }
     for (int j = tid; j < nkeep; j += nt) theta[j] = lam[rank_of[j]];
@@ -442,7 +458,6 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     }
     for (int j = tid; j < nkeep; j += nt) theta[j] = sqrt(fmax(lam[rank_of[j]], 0.0));
   }
-  if (tid == 0) A.status[e] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -696,6 +711,31 @@ __global__ void __launch_bounds__(256) k_copy_rows(const ElemDev* elems, int blk
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= ne) return;
   out[off[e] + (size_t)j * ne + r] = reinterpret_cast<const double*>(E.blk[blk])[(size_t)j * E.ld + r];
+}
+
+// Block roles move with each element: after a rotation the logical blocks of
+// every active element are re-pointed (new[i] = old[perm[i]]); converged
+// elements keep theirs.
+struct Perm8 {
+  int p[kMaxBlocks];
+};
+
+__global__ void k_permute_blocks(ElemDev* elems, int n_elem, const int* active, Perm8 perm) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elem) return;
+  if (active && active[e] <= 0) return;
+  void* old[kMaxBlocks];
+  for (int i = 0; i < kMaxBlocks; ++i) old[i] = elems[e].blk[i];
+  for (int i = 0; i < kMaxBlocks; ++i) elems[e].blk[i] = old[perm.p[i]];
+}
+
+int launch_permute(Ctx& c, const int* perm, const int* active) {
+  Perm8 p;
+  for (int i = 0; i < kMaxBlocks; ++i) p.p[i] = perm[i];
+  hipLaunchKernelGGL(k_permute_blocks, dim3((c.n_elem + 63) / 64), dim3(64), 0, c.stream, c.elems_dev,
+                     c.n_elem, active, p);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(256) k_plane(PlaneArgs A) {
   } else {  // PM_TFWD: r = HX - theta X
     PairCols<T> xx = pair_cols<T>(E, A.in_blk, pair, ncols);
     PairCols<T> hx = pair_cols<T>(E, A.aux_blk, pair, ncols);
-    const double* th = E.small + SmallLayout::vec(A.k3) + VS_THETA * A.k3;
+    const int KP = E.kmax3 + 2;
+    const double* th = E.small + SmallLayout::vec(KP) + VS_THETA * KP;
     const T ta = T(th[2 * pair]);
     const T tb = xx.b ? T(th[2 * pair + 1]) : T(0);
     if (zok) {
@@ -272,7 +273,8 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       v[CV(i)] = {w.a[o], w.b[o]};
     });
     FZ::forward(v, t);
-    const double* ek = E.small + SmallLayout::vec(A.k3) + VS_EKIN * A.k3;
+    const int KP = E.kmax3 + 2;
+    const double* ek = E.small + SmallLayout::vec(KP) + VS_EKIN * KP;
     const double ea = ek[2 * pair];
     const double eb = (2 * pair + 1 < ncols) ? ek[2 * pair + 1] : ea;
     const T inv_e = T(2.0 / (ea + eb));

@@ -1,6 +1,7 @@
 // Host runtime: arena plan, element staging, solver drivers.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -280,6 +281,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->arena_used = P.total;
   c->max_cheb = opt ? std::max(0, opt->max_cheb_degree) : 0;
   c->ckpt_stride = opt ? std::max(1, opt->ckpt_stride) : 1;
+  if (const char* lv = std::getenv("DG_LOG")) c->log_level = std::atoi(lv);
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {

@@ -6,6 +6,9 @@
 #include <string>
 #include <vector>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "dg_internal.h"
 
 namespace dg {
@@ -13,15 +16,6 @@ namespace dg {
 // column-count codes understood by the dense kernels
 constexpr int KC_K = 0;    // E.K
 constexpr int KC_J = -1;   // E.J
-
-// role map: logical block -> physical block
-struct Roles {
-  int r[kMaxBlocks];
-  Roles() {
-    for (int i = 0; i < kMaxBlocks; ++i) r[i] = i;
-  }
-  int operator[](int i) const { return r[i]; }
-};
 
 static int sync_read(Ctx& c, void* dst, const void* src, size_t bytes) {
   DG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
@@ -65,10 +59,10 @@ int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y) {
 // ---------------------------------------------------------------------------
 // LOBPCG (Algorithm 1) for every element at once
 // ---------------------------------------------------------------------------
-static int rr_and_rotate(Ctx& c, int prec, Roles& R, int nb, const int* active, bool lobpcg) {
+static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpcg) {
   int st;
-  ColSet S{nb, {R[B_X], R[B_W], R[B_P]}};
-  ColSet HS{nb, {R[B_HX], R[B_HW], R[B_HP]}};
+  ColSet S{nb, {B_X, B_W, B_P}};
+  ColSet HS{nb, {B_HX, B_HW, B_HP}};
   if ((st = launch_gram(c, prec, S, KC_K, S, KC_K, small_code(0), active))) return st;
   if ((st = launch_gram(c, prec, S, KC_K, HS, KC_K, small_code(1), active))) return st;
   if ((st = launch_rr(c, nb, 0, 0, RR_GEN, active))) return st;
@@ -78,8 +72,8 @@ static int rr_and_rotate(Ctx& c, int prec, Roles& R, int nb, const int* active, 
   ra.S = S;
   ra.kS = KC_K;
   ra.nout = (lobpcg && nb > 1) ? 2 : 1;
-  ra.out_blk[0] = R[B_T0];
-  ra.out_blk[1] = R[B_T1];
+  ra.out_blk[0] = B_T0;
+  ra.out_blk[1] = B_T1;
   ra.c0[0] = 0;
   ra.c1[0] = nb;
   ra.c0[1] = 1;
@@ -93,21 +87,15 @@ static int rr_and_rotate(Ctx& c, int prec, Roles& R, int nb, const int* active, 
   if ((st = launch_rotate(c, prec, ra))) return st;
   // X, P are free now: write HX', HP' there
   ra.S = HS;
-  ra.out_blk[0] = R[B_X];
-  ra.out_blk[1] = R[B_P];
+  ra.out_blk[0] = B_X;
+  ra.out_blk[1] = B_P;
   if ((st = launch_rotate(c, prec, ra))) return st;
-  Roles n = R;
-  n.r[B_X] = R[B_T0];
-  n.r[B_P] = R[B_T1];
-  n.r[B_HX] = R[B_X];
-  n.r[B_HP] = R[B_P];
-  n.r[B_T0] = R[B_HX];
-  n.r[B_T1] = R[B_HP];
-  R = n;
-  return DG_OK;
+  // new X = T0, P = T1, HX = X, HP = P, T0 = HX, T1 = HP
+  int perm[kMaxBlocks] = {B_T0, B_W, B_T1, B_X, B_HW, B_P, B_HX, B_HP};
+  return launch_permute(c, perm, active);
 }
 
-static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int* iters, int* n_done) {
+static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done) {
   int st;
   int* active = c.dev_active;
   // start: H X, then Rayleigh-Ritz on span(X) (orthonormalises X, step 1)
@@ -116,13 +104,13 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int*
     c.host_ints = ones;
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
-  if ((st = launch_hpsi(c, -1, 0, prec, R[B_X], R[B_HX], active))) return st;
-  if ((st = rr_and_rotate(c, prec, R, 1, active, false))) return st;
+  if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
+  if ((st = rr_and_rotate(c, prec, 1, active, false))) return st;
   bool have_p = false;
   std::vector<int> it_elem(c.n_elem, 0);
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    if ((st = launch_residual(c, prec, R[B_X], R[B_HX], 0, active))) return st;
+    if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
     if ((st = launch_check(c, active, tol))) return st;
     int cnt[2];
     if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
@@ -136,19 +124,32 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int*
       for (int e = 0; e < c.n_elem; ++e)
         if (act[e] > 0) it_elem[e] = it;
     }
+    if (c.log_level > 0) {
+      std::vector<double> mr(c.n_elem);
+      std::vector<int> stv(c.n_elem);
+      if ((st = sync_read(c, mr.data(), c.dev_maxres, sizeof(double) * c.n_elem))) return st;
+      if ((st = sync_read(c, stv.data(), c.dev_status, sizeof(int) * c.n_elem))) return st;
+      double m = 0.0;
+      int brk = 0;
+      for (int e = 0; e < c.n_elem; ++e) {
+        m = std::max(m, mr[e]);
+        brk += stv[e] != 0;
+      }
+      fprintf(stderr, "[dg] lobpcg prec=%d it=%d active=%d max_res=%.3e rr_fallbacks=%d\n", prec, it, cnt[0], m, brk);
+    }
     if (cnt[0] == 0) break;
     // W = T(HX - X Theta)  (Eq. (3), step 3)
-    if ((st = launch_teter(c, prec, R[B_X], R[B_HX], R[B_W], 0, active))) return st;
+    if ((st = launch_teter(c, prec, B_X, B_HX, B_W, 0, active))) return st;
     // W <- W - X (X^T W)
     {
-      ColSet SX{1, {R[B_X], 0, 0}}, SW{1, {R[B_W], 0, 0}};
+      ColSet SX{1, {B_X, 0, 0}}, SW{1, {B_W, 0, 0}};
       if ((st = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active))) return st;
       RotArgs ra{};
       ra.active = active;
       ra.S = SX;
       ra.kS = KC_K;
       ra.nout = 1;
-      ra.out_blk[0] = R[B_W];
+      ra.out_blk[0] = B_W;
       ra.c0[0] = 0;
       ra.c1[0] = 1;
       ra.beta[0] = 1.0;
@@ -159,9 +160,9 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int*
       if ((st = launch_rotate(c, prec, ra))) return st;
     }
     // H W
-    if ((st = launch_hpsi(c, -1, 0, prec, R[B_W], R[B_HW], active))) return st;
+    if ((st = launch_hpsi(c, -1, 0, prec, B_W, B_HW, active))) return st;
     // S = [X, W, P], projected problem (Eq. (4)), rotations (Eq. (2))
-    if ((st = rr_and_rotate(c, prec, R, have_p ? 3 : 2, active, true))) return st;
+    if ((st = rr_and_rotate(c, prec, have_p ? 3 : 2, active, true))) return st;
     have_p = true;
   }
   // final residuals for reporting (every element)
@@ -170,7 +171,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int*
     c.host_ints = ones;
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
-  if ((st = launch_residual(c, prec, R[B_X], R[B_HX], 0, active))) return st;
+  if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
   if ((st = launch_check(c, active, tol))) return st;
   int cnt[2];
   if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
@@ -180,7 +181,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, Roles& R, int*
   return cnt[1] > 0 ? DG_ERR_NUMERIC : DG_OK;
 }
 
-int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, Roles& R, int* iters, int* n_done);
+int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters, int* n_done);
 
 int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters) {
   if (!p || !eig || !resid) {
@@ -204,28 +205,29 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
     return DG_ERR_ARG;
   }
   int st;
-  Roles R;
   std::vector<int> it1(c.n_elem, 0), it2(c.n_elem, 0);
   int done = 0;
   if (p->precision == DG_FP64) {
-    if ((st = launch_copy_packed(c, DG_FP64, R[B_X], p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
-    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP64, p->tol, p->max_iter, R, it1.data(), &done)
-                                : run_chfsi(c, DG_FP64, p->tol, p->max_iter, p->cheb_degree, R, it1.data(), &done);
+    if ((st = launch_copy_packed(c, DG_FP64, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
+    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it1.data(), &done)
+                                : run_chfsi(c, DG_FP64, p->tol, p->max_iter, p->cheb_degree, it1.data(), &done);
     if (st < 0) return st;
   } else {
     const double tmp = p->tol_mixed > 0.0 ? p->tol_mixed : 1e-4;
-    if ((st = launch_copy_packed(c, DG_FP32, R[B_X], p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
-    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, R, it1.data(), &done)
-                                : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree, R,
+    if ((st = launch_copy_packed(c, DG_FP32, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
+    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, it1.data(), &done)
+                                : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree,
                                             it1.data(), &done);
     if (st < 0) return st;
     // promote X to FP64 (into W's storage), then FP64 refinement sweeps
-    if ((st = launch_convert(c, R[B_X], DG_FP32, R[B_W], DG_FP64, KC_K))) return st;
-    std::swap(R.r[B_X], R.r[B_W]);
-    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, R, it2.data(), &done);
+    if ((st = launch_convert(c, B_X, DG_FP32, B_W, DG_FP64, KC_K))) return st;
+    {
+      int perm[kMaxBlocks] = {B_W, B_X, B_P, B_HX, B_HW, B_HP, B_T0, B_T1};
+      if ((st = launch_permute(c, perm, nullptr))) return st;
+    }
+    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done);
     if (st < 0) return st;
   }
-  c.roles_x = R[B_X];
   c.solved = true;
   // outputs: theta, residuals of the J wanted states
   if ((st = launch_extract_eig(c, eig, resid))) return st;
@@ -244,7 +246,7 @@ int get_vectors(Ctx& c, double* x) {
     set_error("x_dev is NULL");
     return DG_ERR_ARG;
   }
-  return launch_copy_packed(c, DG_FP64, c.roles_x, x, c.dev_off_vec, KC_J, 1);
+  return launch_copy_packed(c, DG_FP64, B_X, x, c.dev_off_vec, KC_J, 1);
 }
 
 // ALB: gather E_k rows, SVD by eigen-decomposition of the Gram (twice)
@@ -258,11 +260,7 @@ int make_alb(Ctx& c, double* alb, double* sval) {
     return DG_ERR_ARG;
   }
   int st;
-  const int X = c.roles_x;
-  // physical blocks other than X for scratch
-  int t0 = (X == B_T0) ? B_W : B_T0;
-  int t1 = (X == B_T1) ? B_P : B_T1;
-  if (t1 == t0) t1 = B_HW;
+  const int X = B_X, t0 = B_T0, t1 = B_T1;
   if ((st = launch_gather_e(c, X, t0))) return st;
   ColSet S0{1, {t0, 0, 0}}, S1{1, {t1, 0, 0}};
   if ((st = launch_gram_rows(c, DG_FP64, S0, KC_J, S0, KC_J, small_code(0), 1))) return st;
@@ -295,8 +293,8 @@ int make_alb(Ctx& c, double* alb, double* sval) {
 }  // namespace dg
 
 namespace dg {
-int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, Roles& R, int* iters, int* n_done) {
-  (void)c; (void)prec; (void)tol; (void)max_iter; (void)degree; (void)R; (void)iters; (void)n_done;
+int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters, int* n_done) {
+  (void)c; (void)prec; (void)tol; (void)max_iter; (void)degree; (void)iters; (void)n_done;
   set_error("Chebyshev-filtered solver not available in this build");
   return DG_ERR_ARG;
 }
