@@ -190,9 +190,19 @@ int32_t dg_band_energy_backward(dg_ctx *ctx, const double *dE_host, void *dpsi0_
 int32_t dg_set_potential(dg_ctx *ctx, const double *v_dev);
 
 /* Per-kernel-class GPU time accumulated since the last reset, measured with
- * HIP events on the context's stream.  what: 0 = H*psi kernels, 1 = subspace
- * GEMMs, 2 = small dense, 3 = other.  ms_host[4], launches_host[4].  reset != 0
- * clears the counters.  enable != 0 turns timing on (off by default). */
+ * HIP events recorded on the context's stream around each launch group.
+ * Classes (8): 0 plane pass of H*psi (x/y line FFTs + V), 1 z-column pass,
+ * 2 nonlocal overlap/apply, 3 Teter preconditioner (three passes), 4 Gram
+ * GEMMs (+ split reduction), 5 rotations, 6 Rayleigh-Ritz small dense,
+ * 7 other.  ms_host[8], launches_host[8] (may be NULL) receive the totals,
+ * then reset != 0 clears them and enable sets timing on or off (default off).
+ * Synchronises the stream.  Errors: DG_ERR_ARG, DG_ERR_HIP. */
+/* Algorithmic work of the launches timed since the last reset, per class of
+ * dg_timing (8 values): bytes for classes 0-3 (each pass's own minimal reads
+ * and writes), flops for classes 4-5, 0 for 6-7.  Call before a resetting
+ * dg_timing.  Errors: DG_ERR_ARG. */
+int32_t dg_timing_work(dg_ctx *ctx, double *work_host);
+
 int32_t dg_timing(dg_ctx *ctx, int32_t enable, int32_t reset, double *ms_host,
                   int64_t *launches_host);
 

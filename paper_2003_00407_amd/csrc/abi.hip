@@ -150,18 +150,29 @@ int32_t dg_set_potential(dg_ctx* ctx, const double* v_dev) {
   return DG_ERR_ARG;
 }
 
+int32_t dg_timing_work(dg_ctx* ctx, double* work_host) {
+  if (!ctx || !work_host) {
+    dg::set_error("ctx or work_host is NULL");
+    return DG_ERR_ARG;
+  }
+  for (int i = 0; i < dg::TC_N; ++i) work_host[i] = ctx->impl.tacc.work[i];
+  return DG_OK;
+}
+
 int32_t dg_timing(dg_ctx* ctx, int32_t enable, int32_t reset, double* ms_host, int64_t* launches_host) {
   if (!ctx) {
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
   Ctx& c = ctx->impl;
-  c.timing = enable != 0;
+  int st = dg::resolve_timing(c);
+  if (st < 0) return st;
   if (ms_host)
-    for (int i = 0; i < 4; ++i) ms_host[i] = c.tacc.ms[i];
+    for (int i = 0; i < dg::TC_N; ++i) ms_host[i] = c.tacc.ms[i];
   if (launches_host)
-    for (int i = 0; i < 4; ++i) launches_host[i] = c.tacc.launches[i];
+    for (int i = 0; i < dg::TC_N; ++i) launches_host[i] = c.tacc.launches[i];
   if (reset) c.tacc = dg::TimingAcc();
+  c.timing = enable != 0;
   return DG_OK;
 }
 

@@ -72,9 +72,19 @@ struct ShapeClass {
   std::vector<int> elem_list_host;
 };
 
+// kernel classes timed with HIP events when timing is enabled
+enum TimeClass { TC_PLANE = 0, TC_ZCOL = 1, TC_NL = 2, TC_TETER = 3, TC_GRAM = 4, TC_ROT = 5, TC_RR = 6,
+                 TC_OTHER = 7, TC_N = 8 };
+
 struct TimingAcc {
-  double ms[4] = {0, 0, 0, 0};
-  int64_t launches[4] = {0, 0, 0, 0};
+  double ms[TC_N] = {0};
+  int64_t launches[TC_N] = {0};
+  double work[TC_N] = {0};   // algorithmic bytes (passes 0-3) or flops (4-5) of the timed launches
+};
+
+struct PendingTime {
+  int cls;
+  hipEvent_t a, b;
 };
 
 struct Ctx {
@@ -104,7 +114,8 @@ struct Ctx {
   // timing
   bool timing = false;
   TimingAcc tacc;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
+  std::vector<PendingTime> pending;
+  std::vector<hipEvent_t> event_pool;
   // misc device scratch
   int* iota_dev = nullptr;         // 0..n_elem-1
   int* dev_active = nullptr;       // per element solver flags
@@ -117,6 +128,8 @@ struct Ctx {
   long long* dev_off_grid = nullptr;
   long long* dev_off_eig = nullptr;
   std::vector<int> host_ints;      // staging for small async uploads
+  std::vector<int> active_host;    // host mirror of the solver's active flags (work accounting)
+  std::vector<double> nnz;         // projector nonzeros per element
   int roles_x = 0;                 // physical block holding the converged X
   double* gram_part = nullptr;
   long long gram_part_stride = 0;
@@ -126,6 +139,17 @@ struct Ctx {
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable
 };
+
+// RAII: records a HIP event pair around the launches of one kernel class
+struct TimedScope {
+  Ctx& c;
+  int cls;
+  double work;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedScope(Ctx& ctx, int k, double w = 0.0);
+  ~TimedScope();
+};
+int resolve_timing(Ctx& c);
 
 // thread-local error message
 void set_error(const std::string& s);

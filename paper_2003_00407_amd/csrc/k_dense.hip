@@ -763,6 +763,15 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   nsplit = std::min(nsplit, std::max(1, rows / 1024));
   GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, (maxnj + GT - 1) / GT, rows_e, c.gram_part,
               c.gram_part_stride, c.gram_part_ld};
+  double flops = 0.0;
+  for (int e = 0; e < c.n_elem; ++e) {
+    if (active && !c.active_host.empty() && !c.active_host[e]) continue;
+    const int ke = kS > 0 ? kS : (kS == 0 ? c.K[e] : c.J[e]);
+    const int kt = kT > 0 ? kT : (kT == 0 ? c.K[e] : c.J[e]);
+    const double r = rows_e ? (double)c.en[0][e] * c.en[1][e] * c.en[2][e] : (double)c.N[e];
+    flops += 2.0 * r * (S.nb * ke) * (T.nb * kt);
+  }
+  TimedScope ts(c, TC_GRAM, flops);
   dim3 g1(tiles, nsplit, c.n_elem);
   if (prec == DG_FP64) hipLaunchKernelGGL(k_gram<double>, g1, dim3(256), 0, c.stream, ga);
   else hipLaunchKernelGGL(k_gram<float>, g1, dim3(256), 0, c.stream, ga);
@@ -786,6 +795,7 @@ int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
 
 int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) {
   RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status};
+  TimedScope ts(c, TC_RR);
   hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), 0, c.stream, a);
   DG_HIP(hipGetLastError());
   return DG_OK;
@@ -798,6 +808,18 @@ int launch_rotate(Ctx& c, int prec, const RotArgs& a_in) {
   max_dims(c, a.ncol, &k, &maxN, &maxE);
   const int rows = a.rows_e ? maxE : maxN;
   dim3 g((rows + RT_ROWS - 1) / RT_ROWS, c.n_elem);
+  double flops = 0.0;
+  for (int e = 0; e < c.n_elem; ++e) {
+    if (a.active && !c.active_host.empty() && !c.active_host[e]) continue;
+    const int ks = a.kS > 0 ? a.kS : (a.kS == 0 ? c.K[e] : c.J[e]);
+    const int nc = a.ncol > 0 ? a.ncol : (a.ncol == 0 ? c.K[e] : c.J[e]);
+    const double r = a.rows_e ? (double)c.en[0][e] * c.en[1][e] * c.en[2][e] : (double)c.N[e];
+    for (int o = 0; o < a.nout; ++o) {
+      const int span = a.c_blockrows > 0 ? (a.c1[o] - a.c0[o]) * ks : (a.c1[o] - a.c0[o]);
+      flops += 2.0 * r * span * nc;
+    }
+  }
+  TimedScope ts(c, TC_ROT, flops);
   if (prec == DG_FP64) hipLaunchKernelGGL(k_rotate<double>, g, dim3(256), 0, c.stream, a);
   else hipLaunchKernelGGL(k_rotate<float>, g, dim3(256), 0, c.stream, a);
   DG_HIP(hipGetLastError());
@@ -809,6 +831,7 @@ int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int
   max_dims(c, ncol, &maxk, &maxN, &maxE);
   ResArgs a{c.elems_dev, active, x_blk, hx_blk, ncol, 0};
   dim3 g(maxk, c.n_elem);
+  TimedScope ts(c, TC_OTHER);
   if (prec == DG_FP64) hipLaunchKernelGGL(k_residual<double>, g, dim3(256), 0, c.stream, a);
   else hipLaunchKernelGGL(k_residual<float>, g, dim3(256), 0, c.stream, a);
   DG_HIP(hipGetLastError());

@@ -463,9 +463,30 @@ static bool dispatch_z(int nz, const ZArgs& a, int nxy, int npairs, int nel, hip
   }
 }
 
+// algorithmic bytes of the H*psi passes for the elements a launch covers
+struct HpsiWork {
+  double plane = 0, zcol = 0, nl = 0;
+};
+
+static HpsiWork hpsi_work(Ctx& c, int elem, int ncols, size_t sz, const std::vector<int>& members,
+                          const int* active_host) {
+  HpsiWork w;
+  for (int e : members) {
+    if (elem >= 0 && e != elem) continue;
+    if (active_host && !active_host[e]) continue;
+    const double N = c.N[e], k = ncols > 0 ? ncols : c.K[e];
+    w.plane += (2.0 * k + 1.0) * N * sz;          // read x, write y1, read V
+    w.zcol += 3.0 * k * N * sz;                   // read x, read y1, write y
+    const double nnz = c.nnz[e], nact = c.elems_host[e].nact;
+    w.nl += nnz * (sz + 4) + 3.0 * nact * k * sz;  // projectors; x read, y read+write at active points
+  }
+  return w;
+}
+
 template <typename T>
 static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, const int* active) {
   hipStream_t s = c.stream;
+  const int* act_host = (active && !c.active_host.empty()) ? c.active_host.data() : nullptr;
   const int* iota = c.iota_dev;
   // projector overlaps first (reads x only)
   {
@@ -478,6 +499,9 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
       kk = std::max(kk, ncols > 0 ? ncols : c.K[e]);
     }
     if (ng > 0) {
+      std::vector<int> all(c.n_elem);
+      for (int e = 0; e < c.n_elem; ++e) all[e] = e;
+      TimedScope ts(c, TC_NL, hpsi_work(c, elem, ncols, sizeof(T), all, act_host).nl);
       dim3 g1(ng, (kk + kNlCols - 1) / kNlCols, elem >= 0 ? 1 : c.n_elem);
       hipLaunchKernelGGL(k_nl_overlap<T>, g1, dim3(256), 0, s, na);
     }
@@ -500,14 +524,21 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
     }
     const int npairs = (maxk + 1) / 2;
     PlaneArgs pa{c.elems_dev, list, active, in_blk, out_blk, -1, ncols, nullptr, 0};
-    if (!dispatch_plane<T, PM_HPSI>(sc.nx, pa, sc.nz, npairs, nel, s)) {
-      set_error("unsupported grid");
-      return DG_ERR_SHAPE;
+    const HpsiWork hw = hpsi_work(c, elem, ncols, sizeof(T), sc.elem_list_host, act_host);
+    {
+      TimedScope ts(c, TC_PLANE, hw.plane);
+      if (!dispatch_plane<T, PM_HPSI>(sc.nx, pa, sc.nz, npairs, nel, s)) {
+        set_error("unsupported grid");
+        return DG_ERR_SHAPE;
+      }
     }
     ZArgs za{c.elems_dev, list, active, in_blk, out_blk, ncols, 0};
-    if (!dispatch_z<T, ZM_HPSI>(sc.nz, za, sc.nx * sc.ny, npairs, nel, s)) {
-      set_error("unsupported grid");
-      return DG_ERR_SHAPE;
+    {
+      TimedScope ts(c, TC_ZCOL, hw.zcol);
+      if (!dispatch_z<T, ZM_HPSI>(sc.nz, za, sc.nx * sc.ny, npairs, nel, s)) {
+        set_error("unsupported grid");
+        return DG_ERR_SHAPE;
+      }
     }
   }
   if (c.nl_pending_np > 0) {
@@ -518,6 +549,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
     dim3 g2((nact + 255) / 256, (c.nl_pending_kk + kNlApplyCols - 1) / kNlApplyCols,
             elem >= 0 ? 1 : c.n_elem);
     size_t shm = (size_t)c.nl_pending_np * kNlApplyCols * sizeof(double);
+    TimedScope ts(c, TC_NL);
     hipLaunchKernelGGL(k_nl_apply<T>, g2, dim3(256), shm, s, na);
   }
   DG_HIP(hipGetLastError());
@@ -533,6 +565,10 @@ int launch_hpsi(Ctx& c, int elem, int ncols, int prec, int in_blk, int out_blk, 
 template <typename T>
 static int teter_typed(Ctx& c, int x_blk, int hx_blk, int w_blk, int k3, const int* active) {
   hipStream_t s = c.stream;
+  double tw = 0.0;
+  for (int e = 0; e < c.n_elem; ++e)
+    if (c.active_host.empty() || c.active_host[e]) tw += 3.0 * c.K[e] * (double)c.N[e] * sizeof(T);
+  TimedScope ts(c, TC_TETER, tw);   // read X, HX, write W
   for (const ShapeClass& sc : c.classes) {
     const int npairs = (sc.max_k + 1) / 2;
     PlaneArgs pa{c.elems_dev, sc.elem_list_dev, active, x_blk, w_blk, hx_blk, -1, nullptr, k3};

@@ -17,6 +17,48 @@ const char* get_error() { return g_err.c_str(); }
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+static hipEvent_t get_event(Ctx& c) {
+  if (!c.event_pool.empty()) {
+    hipEvent_t e = c.event_pool.back();
+    c.event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+TimedScope::TimedScope(Ctx& ctx, int k, double w) : c(ctx), cls(k), work(w) {
+  if (!c.timing) return;
+  a = get_event(c);
+  b = get_event(c);
+  if (a) hipEventRecord(a, c.stream);
+}
+
+TimedScope::~TimedScope() {
+  if (!c.timing || !a || !b) return;
+  hipEventRecord(b, c.stream);
+  c.pending.push_back({cls, a, b});
+  c.tacc.work[cls] += work;
+  if (c.pending.size() > 20000) resolve_timing(c);
+}
+
+int resolve_timing(Ctx& c) {
+  if (c.pending.empty()) return DG_OK;
+  DG_HIP(hipStreamSynchronize(c.stream));
+  for (const PendingTime& p : c.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c.tacc.ms[p.cls] += ms;
+      c.tacc.launches[p.cls] += 1;
+    }
+    c.event_pool.push_back(p.a);
+    c.event_pool.push_back(p.b);
+  }
+  c.pending.clear();
+  return DG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // host-side projector preprocessing: groups of projectors with one support,
 // and the transposed (grid-point-major) entry lists.
@@ -360,6 +402,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
     c->N[e] = p.N;
     c->ld[e] = p.ld;
     c->kmax = std::max(c->kmax, p.K);
+    c->nnz.push_back(x.n_proj > 0 ? (double)x.proj_ptr[x.n_proj] : 0.0);
     if ((st = cpy(p.off_v64, x.v_eff, sizeof(double) * p.N))) return st;
     keep32.emplace_back(x.v_eff, x.v_eff + p.N);
     if ((st = cpy(p.off_v32, keep32.back().data(), sizeof(float) * p.N))) return st;

@@ -104,6 +104,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     c.host_ints = ones;
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
+  c.active_host.assign(c.n_elem, 1);
   if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
   if ((st = rr_and_rotate(c, prec, 1, active, false))) return st;
   bool have_p = false;
@@ -123,6 +124,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
       if ((st = sync_read(c, act.data(), active, sizeof(int) * c.n_elem))) return st;
       for (int e = 0; e < c.n_elem; ++e)
         if (act[e] > 0) it_elem[e] = it;
+      c.active_host = act;
     }
     if (c.log_level > 0) {
       std::vector<double> mr(c.n_elem);
@@ -165,6 +167,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     if ((st = rr_and_rotate(c, prec, have_p ? 3 : 2, active, true))) return st;
     have_p = true;
   }
+  c.active_host.clear();
   // final residuals for reporting (every element)
   {
     std::vector<int> ones(c.n_elem, 1);

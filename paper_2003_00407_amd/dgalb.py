@@ -29,7 +29,7 @@ DG_OFF_X0, DG_OFF_VEC, DG_OFF_EIG, DG_OFF_ALB, DG_OFF_GRID, DG_OFF_KALL = range(
 EXPORTED = [
     "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
     "dg_query_offsets", "dg_apply_H", "dg_solve_elements", "dg_get_vectors", "dg_make_alb",
-    "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing",
+    "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing", "dg_timing_work",
 ]
 
 
@@ -73,6 +73,7 @@ _lib.dg_band_energy.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_
 _lib.dg_band_energy_backward.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
 _lib.dg_set_potential.argtypes = [C.c_void_p, C.c_void_p]
 _lib.dg_timing.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+_lib.dg_timing_work.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
 
 
 class DGError(RuntimeError):
@@ -219,11 +220,16 @@ class Elements:
                "dg_make_alb")
         return alb, sv
 
+    TIMING_CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
+
     def timing(self, enable: bool = True, reset: bool = False):
-        ms = (C.c_double * 4)()
-        n = (C.c_int64 * 4)()
+        """(ms, launches, algorithmic work) per class since the last reset; then reset/enable."""
+        ms = (C.c_double * 8)()
+        n = (C.c_int64 * 8)()
+        w = (C.c_double * 8)()
+        _check(_lib.dg_timing_work(self.ctx, w), "dg_timing_work")
         _check(_lib.dg_timing(self.ctx, int(enable), int(reset), ms, n), "dg_timing")
-        return list(ms), list(n)
+        return list(ms), list(n), list(w)
 
 
 def pack_initial(elements: Sequence, seed_base: int, n_guard: int = -1):
