@@ -138,6 +138,9 @@ struct Ctx {
   int nl_pending_np = 0, nl_pending_kk = 0;
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable
+  double rr_pivot_tol = 1e-13;     // overlap-Cholesky breakdown threshold (FP64 data)
+  double rr_ortol = 1e-3;          // cluster tolerance of the inverse iteration (relative to ||T||)
+  long long* dev_phase = nullptr;  // diagnostics: RR phase timestamps (8 per element)
 };
 
 // RAII: records a HIP event pair around the launches of one kernel class
@@ -192,13 +195,13 @@ struct RotArgs {
   int rows_e;          // 1: the first |E_k| rows only
 };
 int launch_gram(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
-                long long out_off, const int* active);
+                long long out_off, const int* active, int sym);
 int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active);
 int launch_rotate(Ctx& c, int prec, const RotArgs& a);
 int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int* active);
 int launch_check(Ctx& c, int* active, double tol);
 int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
-                     long long out_off, int rows_e);
+                     long long out_off, int rows_e, int sym);
 int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed);
 int launch_copy_packed(Ctx& c, int prec, int blk, const double* ptr, const long long* off, int ncol,
                        int to_packed);

@@ -11,6 +11,7 @@
 //  * Rotations X <- S C (Eq. (2), Algorithm 1 steps 6-7; Algorithm 2 step 5).
 //  * Residual norms ||H x_i - theta_i x_i|| and the preconditioner energy.
 #include "dg_internal.h"
+#include "tridiag.h"
 
 #include <algorithm>
 
@@ -55,12 +56,22 @@ struct GramArgs {
   int nsplit;
   int tiles_j;         // output tile columns of the launch grid
   int rows_e;          // 1: reduce over the first |E_k| rows only
+  int sym;             // 1: S == T, only tiles with ti <= tj are computed
   double* part;        // per element region of part_stride doubles
   long long part_stride;
   int part_ld;         // leading dim of a partial tile matrix
 };
 
-constexpr int GT = 32;  // Gram tile
+constexpr int GT = 32;   // Gram output tile (4 waves x 16x16 MFMA sub-tiles)
+constexpr int GR = 64;   // rows staged per step
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 lane layout (checked on the device): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; result register q of lane l is D[l/16 + 4q][l%16].
+__device__ __forceinline__ d4v mfma16x16x4(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram(GramArgs A) {
@@ -72,57 +83,59 @@ __global__ void __launch_bounds__(256) k_gram(GramArgs A) {
   const int ni = A.S.nb * kS, nj = A.T.nb * kT;
   const int ti = blockIdx.x / A.tiles_j, tj = blockIdx.x % A.tiles_j;
   if (ti * GT >= ni || tj * GT >= nj) return;
+  if (A.sym && ti > tj) return;          // symmetric product: upper tiles only
   const int split = blockIdx.y;
   const int nrows = nrows_of(E, A.rows_e);
-  const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GT - 1) / GT * GT;
+  const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GR - 1) / GR * GR;
   const int r0 = split * rows_per;
   const int r1 = min(nrows, r0 + rows_per);
-  __shared__ double sa[GT][GT + 1];
-  __shared__ double sb[GT][GT + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc00 = 0, acc01 = 0, acc10 = 0, acc11 = 0;
-  const T* colA[4];
-  const T* colB[4];
-  int lrow[4], lcol[4];
+  __shared__ double sa[GR][GT + 1];
+  __shared__ double sb[GR][GT + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  // each thread stages 8 values per matrix: column idx/GR, row idx%GR (coalesced along rows)
+  const T* colA[8];
+  const T* colB[8];
+  int lrow[8], lcol[8];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 8; ++q) {
     const int idx = threadIdx.x + 256 * q;
-    lcol[q] = idx / GT;
-    lrow[q] = idx % GT;
+    lcol[q] = idx / GR;
+    lrow[q] = idx % GR;
     const int ci = ti * GT + lcol[q], cj = tj * GT + lcol[q];
     colA[q] = ci < ni ? vcol<T>(E, A.S, ci, kS) : nullptr;
     colB[q] = cj < nj ? vcol<T>(E, A.T, cj, kT) : nullptr;
   }
-  for (int r = r0; r < r1; r += GT) {
+  d4v acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r = r0; r < r1; r += GR) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int rr = r + lrow[q];
-      sa[lcol[q]][lrow[q]] = (colA[q] && rr < r1) ? double(colA[q][rr]) : 0.0;
-      sb[lcol[q]][lrow[q]] = (colB[q] && rr < r1) ? double(colB[q][rr]) : 0.0;
+      sa[lrow[q]][lcol[q]] = (colA[q] && rr < r1) ? double(colA[q][rr]) : 0.0;
+      sb[lrow[q]][lcol[q]] = (colB[q] && rr < r1) ? double(colB[q][rr]) : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < GT; ++k) {
-      const double a0 = sa[2 * ty][k], a1 = sa[2 * ty + 1][k];
-      const double b0 = sb[2 * tx][k], b1 = sb[2 * tx + 1][k];
-      acc00 += a0 * b0;
-      acc01 += a0 * b1;
-      acc10 += a1 * b0;
-      acc11 += a1 * b1;
+#pragma unroll
+    for (int ks = 0; ks < GR / 4; ++ks) {
+      const double av = sa[ks * 4 + (lane >> 4)][wi * 16 + (lane & 15)];
+      const double bv = sb[ks * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+      acc = mfma16x16x4(av, bv, acc);
     }
     __syncthreads();
   }
   double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
-  const int i0 = ti * GT + 2 * ty, j0 = tj * GT + 2 * tx;
-  if (i0 < ni && j0 < nj) out[(size_t)i0 * A.part_ld + j0] = acc00;
-  if (i0 < ni && j0 + 1 < nj) out[(size_t)i0 * A.part_ld + j0 + 1] = acc01;
-  if (i0 + 1 < ni && j0 < nj) out[(size_t)(i0 + 1) * A.part_ld + j0] = acc10;
-  if (i0 + 1 < ni && j0 + 1 < nj) out[(size_t)(i0 + 1) * A.part_ld + j0 + 1] = acc11;
+  const int j = tj * GT + wj * 16 + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = ti * GT + wi * 16 + (lane >> 4) + 4 * q;
+    if (i < ni && j < nj) out[(size_t)i * A.part_ld + j] = acc[q];
+  }
 }
 
 struct GramReduceArgs {
   const ElemDev* elems;
   const int* active;
+  int sym;
   int nbS, nbT, kS, kT;
   int nsplit;
   const double* part;
@@ -143,7 +156,9 @@ __global__ void __launch_bounds__(256) k_gram_reduce(GramReduceArgs A) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= ni * nj) return;
   const int i = idx / nj, j = idx % nj;
-  const double* p = A.part + (size_t)e * A.part_stride + (size_t)i * A.part_ld + j;
+  const bool mirror = A.sym && (i / GT) > (j / GT);
+  const double* p = A.part + (size_t)e * A.part_stride +
+                    (mirror ? (size_t)j * A.part_ld + i : (size_t)i * A.part_ld + j);
   double s = 0.0;
   for (int q = 0; q < A.nsplit; ++q) s += p[(size_t)q * A.part_ld * A.part_ld];
   E.small[soff(A.out_off, E) + (size_t)i * ld + j] = s;
@@ -196,23 +211,16 @@ struct RRArgs {
   int mode;
   int max_sweeps;
   int* status;         // per element: 0 ok, 1 breakdown
+  int lds_order;       // > 0: the Jacobi matrix lives in dynamic LDS when np <= lds_order
+  long long* phase_clk;  // optional: 8 timestamps per element (diagnostics)
+  double* work;          // per element work region (inverse iteration)
+  long long work_stride;
+  double pivot_tol;      // overlap Cholesky pivots below this (after unit-diagonal scaling) = breakdown
+  double ortol;          // eigenvalues closer than ortol * ||T|| are treated as one cluster
 };
 
 constexpr int kRRThreads = 512;
-
-__device__ __forceinline__ void jacobi_cs(double app, double aqq, double apq, double& c, double& s,
-                                          double& t) {
-  if (apq == 0.0) {
-    c = 1.0;
-    s = 0.0;
-    t = 0.0;
-    return;
-  }
-  const double th = (aqq - app) / (2.0 * apq);
-  t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-  c = 1.0 / sqrt(1.0 + t * t);
-  s = t * c;
-}
+constexpr int kTriMax = 272;   // largest projected problem handled (3 x 88 + pad)
 
 __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
   const int e = blockIdx.x;
@@ -230,13 +238,13 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
   double* Cm = E.small + SmallLayout::C(KP);
   double* vec = E.small + SmallLayout::vec(KP);
   double* d = vec + VS_D * KP;
-  double* lam = vec + VS_T0 * KP;
-  double* csv = vec + VS_T1 * KP;   // c of each pair
-  double* ssv = vec + VS_T2 * KP;   // s of each pair
-  double* tsv = vec + VS_T2 * KP + KP / 2 + 1;
   __shared__ double sh[16];
   __shared__ int brk;
   const int tid = threadIdx.x, nt = blockDim.x;
+  auto stamp = [&](int k) {
+    if (A.phase_clk && tid == 0) A.phase_clk[e * 8 + k] = wall_clock64();
+  };
+  stamp(0);
   // Inputs: G and A (n x n, ld n) as written by the Gram reduction.  For the
   // generalised problem the leading blocks of S are tried in turn when the
   // overlap Cholesky breaks down: [X W P], then [X W], then [X]; the
@@ -270,7 +278,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
       // Cholesky (upper, in place in Um): Um = U^T U
       for (int j = 0; j < m; ++j) {
         const double piv = Um[(size_t)j * np + j];
-        if (!(piv > 1e-13) && tid == 0) brk = 1;
+        if (!(piv > A.pivot_tol) && tid == 0) brk = 1;
         const double ujj = sqrt(fmax(piv, 1e-300));
         __syncthreads();
         for (int k = j + 1 + tid; k < m; k += nt) Um[(size_t)j * np + k] /= ujj;
@@ -288,39 +296,51 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
       if (n_cur > K) {
         n_cur -= K;
       } else {
+        // unrecoverable: keep X (C = [I; 0; 0]) and report the status
+        for (int idx = tid; idx < n * nkeep; idx += nt) {
+          const int i = idx / nkeep, j = idx % nkeep;
+          Cm[idx] = (i == j) ? 1.0 : 0.0;
+        }
         if (tid == 0) A.status[e] = 2;
-        return;   // unrecoverable: C is left as is and the status reports it
+        return;
       }
       __syncthreads();
     }
     if (tid == 0) A.status[e] = attempt;
+    stamp(1);
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
       if (j < i) Um[idx] = 0.0;
     }
     __syncthreads();
-    // Z = U^{-1} (upper), column j by back substitution, into G (inputs are no longer needed)
-    for (int j = tid; j < np; j += nt) {
-      for (int i = np - 1; i >= 0; --i) {
-        double s = (i == j) ? 1.0 : 0.0;
-        for (int k = i + 1; k <= j; ++k) s -= Um[(size_t)i * np + k] * G[(size_t)k * np + j];
-        G[(size_t)i * np + j] = (i <= j) ? s / Um[(size_t)i * np + i] : 0.0;
-      }
-    }
+    // Z = U^{-1} (upper) into G, one row per step from the bottom (rows below are final)
+    for (int idx = tid; idx < np * np; idx += nt) G[idx] = 0.0;
     __syncthreads();
+    for (int i = n_cur - 1; i >= 0; --i) {
+      const double uii = Um[(size_t)i * np + i];
+      for (int j = i + tid; j < n_cur; j += nt) {
+        double sacc = (i == j) ? 1.0 : 0.0;
+        for (int k = i + 1; k <= j; ++k) sacc -= Um[(size_t)i * np + k] * G[(size_t)k * np + j];
+        G[(size_t)i * np + j] = sacc / uii;
+      }
+      __syncthreads();
+    }
+    stamp(2);
     // Am = A' Z ; Um = Z^T Am ; Am = sym(Um)  (standard problem)
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
-      double s = 0.0;
-      for (int k = 0; k <= j; ++k) s += Vm[(size_t)i * np + k] * G[(size_t)k * np + j];
-      Am[idx] = s;
+      double sacc = 0.0;
+      if (i < n_cur && j < n_cur)
+        for (int k = 0; k <= j; ++k) sacc += Vm[(size_t)i * np + k] * G[(size_t)k * np + j];
+      Am[idx] = sacc;
     }
     __syncthreads();
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
-      double s = 0.0;
-      for (int k = 0; k <= i; ++k) s += G[(size_t)k * np + i] * Am[(size_t)k * np + j];
-      Um[idx] = s;
+      double sacc = 0.0;
+      if (i < n_cur && j < n_cur)
+        for (int k = 0; k <= i; ++k) sacc += G[(size_t)k * np + i] * Am[(size_t)k * np + j];
+      Um[idx] = sacc;
     }
     __syncthreads();
     for (int idx = tid; idx < np * np; idx += nt) {
@@ -331,143 +351,233 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     // RR_SVD: eigen-decomposition of the Gram matrix itself
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
-      Um[idx] = (i < n && j < n) ? G[(size_t)i * n + j] : 0.0;
+      Am[idx] = (i < n && j < n) ? G[(size_t)i * n + j] : 0.0;
+    }
+  }
+  __syncthreads();
+  stamp(3);
+  // ---- symmetric eigen-solve of the n_cur x n_cur matrix Am
+  const int m_eig = n_cur;
+  // work matrix in LDS when it fits
+  extern __shared__ double lds_dyn[];
+  double* Aj = Am;
+  if (np <= A.lds_order) {
+    for (int idx = tid; idx < np * np; idx += nt) lds_dyn[idx] = Am[idx];
+    Aj = lds_dyn;
+  }
+  __shared__ double sd[kTriMax], se[kTriMax], stau[kTriMax];
+  __shared__ double vs[kTriMax], ps[kTriMax], ws[kTriMax];
+  __syncthreads();
+  // (1) Householder tridiagonalisation; reflector k kept in column k below the diagonal
+  for (int kk = 0; kk < m_eig - 2; ++kk) {
+    const int m = m_eig - kk - 1;
+    double part = 0.0;
+    for (int i = tid; i < m; i += nt) {
+      const double x = Aj[(size_t)(kk + 1 + i) * np + kk];
+      part += x * x;
+    }
+    const double ss = block_sum(part, sh);
+    const double x0 = Aj[(size_t)(kk + 1) * np + kk];
+    if (tid == 0) sd[kk] = Aj[(size_t)kk * np + kk];
+    if (ss == 0.0) {
+      if (tid == 0) {
+        stau[kk] = 0.0;
+        se[kk] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
+    const double vv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+    const double tau = 2.0 / vv;
+    for (int i = tid; i < m; i += nt) vs[i] = (i == 0) ? x0 - alpha : Aj[(size_t)(kk + 1 + i) * np + kk];
+    if (tid == 0) {
+      stau[kk] = tau;
+      se[kk] = alpha;
     }
     __syncthreads();
-    for (int idx = tid; idx < np * np; idx += nt) Am[idx] = Um[idx];
-  }
-  __syncthreads();
-  // ---- cyclic Jacobi, round-robin pairs, V accumulated in Vm
-  for (int idx = tid; idx < np * np; idx += nt) {
-    const int i = idx / np, j = idx % np;
-    Vm[idx] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int half = np / 2;
-  for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      const double a = Am[idx];
-      if (i != j) off += a * a;
-      else dia += a * a;
+    for (int i = tid; i < m; i += nt) {
+      const double* row = Aj + (size_t)(kk + 1 + i) * np + kk + 1;
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += row[j] * vs[j];
+      ps[i] = tau * acc;
     }
-    off = block_sum(off, sh);
-    dia = block_sum(dia, sh);
-    if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int r = 0; r < np - 1; ++r) {
-      for (int pi = tid; pi < half; pi += nt) {
-        const int a = pi, b = np - 1 - pi;
-        const int ia = a == 0 ? 0 : ((a - 1 + r) % (np - 1)) + 1;
-        const int ib = b == 0 ? 0 : ((b - 1 + r) % (np - 1)) + 1;
-        const int p = min(ia, ib), q = max(ia, ib);
-        double c, s, t;
-        jacobi_cs(Am[(size_t)p * np + p], Am[(size_t)q * np + q], Am[(size_t)p * np + q], c, s, t);
-        csv[pi] = c;
-        ssv[pi] = s;
-        tsv[pi] = t;
-      }
-      __syncthreads();
-      // 2x2 block updates A' = J^T A J over all (pair i, pair j) blocks; then V J
-      for (int idx = tid; idx < half * half + half * np; idx += nt) {
-        if (idx < half * half) {
-          const int bi = idx / half, bj = idx % half;
-          auto pq = [&](int pi, int& p, int& q) {
-            const int a = pi, b = np - 1 - pi;
-            const int ia = a == 0 ? 0 : ((a - 1 + r) % (np - 1)) + 1;
-            const int ib = b == 0 ? 0 : ((b - 1 + r) % (np - 1)) + 1;
-            p = min(ia, ib);
-            q = max(ia, ib);
-          };
-          int pI, qI, pJ, qJ;
-          pq(bi, pI, qI);
-          pq(bj, pJ, qJ);
-          const double ci = csv[bi], si = ssv[bi], cj = csv[bj], sj = ssv[bj];
-          double* a00 = &Am[(size_t)pI * np + pJ];
-          double* a01 = &Am[(size_t)pI * np + qJ];
-          double* a10 = &Am[(size_t)qI * np + pJ];
-          double* a11 = &Am[(size_t)qI * np + qJ];
-          if (bi == bj) {
-            const double t = tsv[bi];
-            const double apq = *a01;
-            *a00 = *a00 - t * apq;
-            *a11 = *a11 + t * apq;
-            *a01 = 0.0;
-            *a10 = 0.0;
-          } else {
-            const double m00 = *a00, m01 = *a01, m10 = *a10, m11 = *a11;
-            const double b00 = ci * m00 - si * m10, b01 = ci * m01 - si * m11;
-            const double b10 = si * m00 + ci * m10, b11 = si * m01 + ci * m11;
-            *a00 = cj * b00 - sj * b01;
-            *a01 = sj * b00 + cj * b01;
-            *a10 = cj * b10 - sj * b11;
-            *a11 = sj * b10 + cj * b11;
-          }
-        } else {
-          const int k = idx - half * half;
-          const int row = k / half, pj = k % half;
-          const int a = pj, b = np - 1 - pj;
-          const int ia = a == 0 ? 0 : ((a - 1 + r) % (np - 1)) + 1;
-          const int ib = b == 0 ? 0 : ((b - 1 + r) % (np - 1)) + 1;
-          const int p = min(ia, ib), q = max(ia, ib);
-          const double c = csv[pj], s = ssv[pj];
-          const double vp = Vm[(size_t)row * np + p], vq = Vm[(size_t)row * np + q];
-          Vm[(size_t)row * np + p] = c * vp - s * vq;
-          Vm[(size_t)row * np + q] = s * vp + c * vq;
+    __syncthreads();
+    double kp = 0.0;
+    for (int i = tid; i < m; i += nt) kp += vs[i] * ps[i];
+    const double Kc = 0.5 * tau * block_sum(kp, sh);
+    for (int i = tid; i < m; i += nt) ws[i] = ps[i] - Kc * vs[i];
+    __syncthreads();
+    for (int idx = tid; idx < m * m; idx += nt) {
+      const int i = idx / m, j = idx % m;
+      Aj[(size_t)(kk + 1 + i) * np + kk + 1 + j] -= vs[i] * ws[j] + ws[i] * vs[j];
+    }
+    for (int i = tid; i < m; i += nt) Aj[(size_t)(kk + 1 + i) * np + kk] = vs[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (m_eig >= 2) {
+      sd[m_eig - 2] = Aj[(size_t)(m_eig - 2) * np + m_eig - 2];
+      se[m_eig - 2] = Aj[(size_t)(m_eig - 1) * np + m_eig - 2];
+      stau[m_eig - 2] = 0.0;
+    }
+    sd[m_eig - 1] = Aj[(size_t)(m_eig - 1) * np + m_eig - 1];
+    se[m_eig - 1] = 0.0;
+  }
+  __syncthreads();
+  // (2) eigenvalues by bisection on Sturm counts (thread j -> j-th smallest)
+  __shared__ double sb_lo, sb_hi, sb_norm;
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300, nrm = 0.0;
+    for (int i = 0; i < m_eig; ++i) {
+      const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m_eig - 1 ? fabs(se[i]) : 0.0);
+      lo = fmin(lo, sd[i] - r);
+      hi = fmax(hi, sd[i] + r);
+      nrm = fmax(nrm, fabs(sd[i]) + r);
+    }
+    sb_norm = fmax(nrm, 1e-300);
+    sb_lo = lo - 1e-12 * sb_norm - 1e-300;
+    sb_hi = hi + 1e-12 * sb_norm + 1e-300;
+  }
+  __syncthreads();
+  const double onenorm = sb_norm;
+  const double pivmin = 1e-300 + 1e-30 * onenorm * onenorm;
+  // eigen-indices wanted: the nkeep smallest (RR_GEN) or all (RR_SVD)
+  const int nwant = (A.mode == RR_GEN) ? min(nkeep, m_eig) : m_eig;
+  double* lam_s = vec + VS_FLAGS * KP;           // eigenvalues, ascending
+  for (int j = tid; j < nwant; j += nt) lam_s[j] = bisect_eig(sd, se, m_eig, j, sb_lo, sb_hi, pivmin);
+  __syncthreads();
+  // (3) eigenvectors of T by inverse iteration; clusters re-orthogonalised in order
+  __shared__ int cst[kTriMax];
+  __shared__ double shf[kTriMax];
+  __shared__ int maxrank;
+  if (tid == 0) {
+    // eigenvalues closer than ortol * ||T|| form a cluster whose vectors are
+    // computed in order, each re-orthogonalised against the earlier ones
+    const double ortol = A.ortol * onenorm, pertol = 10.0 * 2.2e-16 * onenorm;
+    int mr = 0;
+    for (int j = 0; j < nwant; ++j) {
+      cst[j] = (j > 0 && lam_s[j] - lam_s[j - 1] <= ortol) ? cst[j - 1] : j;
+      shf[j] = lam_s[j];
+      if (j > 0 && cst[j] != j && shf[j] < shf[j - 1] + pertol) shf[j] = shf[j - 1] + pertol;
+      mr = max(mr, j - cst[j]);
+    }
+    maxrank = mr;
+  }
+  __syncthreads();
+  double* Zv = Um;   // eigenvector j of T at Zv[j * np + i]
+  for (int rnd = 0; rnd <= maxrank; ++rnd) {
+    for (int j = tid; j < nwant; j += nt) {
+      if (j - cst[j] != rnd) continue;
+      // per-thread arrays, interleaved across threads so a wave's accesses coalesce
+      double* wk = A.work + (size_t)e * A.work_stride;
+      StridedD ta{wk + 0 * (size_t)np * kRRThreads + j, kRRThreads};
+      StridedD tb{wk + 1 * (size_t)np * kRRThreads + j, kRRThreads};
+      StridedD tu{wk + 2 * (size_t)np * kRRThreads + j, kRRThreads};
+      StridedD tl{wk + 3 * (size_t)np * kRRThreads + j, kRRThreads};
+      StridedD z{wk + 4 * (size_t)np * kRRThreads + j, kRRThreads};
+      StridedB pv{reinterpret_cast<unsigned char*>(wk + 5 * (size_t)np * kRRThreads) + j, kRRThreads};
+      tri_lu(sd, se, m_eig, shf[j], 2.2e-16 * onenorm, ta, tb, tu, tl, pv);
+      for (int i = 0; i < m_eig; ++i) z[i] = hash_unit(j, i);
+      for (int it = 0; it < 4; ++it) {
+        tri_solve(m_eig, ta, tb, tu, tl, pv, z);
+        for (int q = cst[j]; q < j; ++q) {
+          const double* zq = Zv + (size_t)q * np;
+          double dot = 0.0;
+          for (int i = 0; i < m_eig; ++i) dot += zq[i] * z[i];
+          for (int i = 0; i < m_eig; ++i) z[i] -= dot * zq[i];
         }
+        double nn = 0.0;
+        for (int i = 0; i < m_eig; ++i) nn += z[i] * z[i];
+        nn = 1.0 / sqrt(nn);
+        for (int i = 0; i < m_eig; ++i) z[i] *= nn;
       }
-      __syncthreads();
+      for (int i = 0; i < np; ++i) Zv[(size_t)j * np + i] = (i < m_eig) ? z[i] : 0.0;
+    }
+    __syncthreads();
+  }
+  // in-order modified Gram-Schmidt of the eigenvectors of T (one vector at a time,
+  // the whole workgroup cooperating)
+  for (int j = 1; j < nwant; ++j) {
+    double* zj = Zv + (size_t)j * np;
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    for (int q = wv; q < j; q += nw) {
+      const double* zq = Zv + (size_t)q * np;
+      double dot = 0.0;
+      for (int i = lane; i < m_eig; i += 64) dot += zq[i] * zj[i];
+      dot = wave_sum(dot);
+      if (lane == 0) ps[q] = dot;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int i = tid; i < m_eig; i += nt) {
+      double v = zj[i];
+      for (int q = 0; q < j; ++q) v -= ps[q] * Zv[(size_t)q * np + i];
+      zj[i] = v;
+      part += v * v;
+    }
+    const double nn = 1.0 / sqrt(block_sum(part, sh));
+    for (int i = tid; i < m_eig; i += nt) zj[i] *= nn;
+    __syncthreads();
+  }
+  // (4) back-transform: z <- H_0 ... H_{m-3} z (one wave per vector, lanes over rows)
+  {
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    for (int j = wv; j < nwant; j += nw) {
+      double* z = Zv + (size_t)j * np;
+      for (int kk = m_eig - 3; kk >= 0; --kk) {
+        const double tau = stau[kk];
+        if (tau == 0.0) continue;
+        double dot = 0.0;
+        for (int i = kk + 1 + lane; i < m_eig; i += 64) dot += Aj[(size_t)i * np + kk] * z[i];
+        dot = wave_sum(dot) * tau;
+        for (int i = kk + 1 + lane; i < m_eig; i += 64) z[i] -= dot * Aj[(size_t)i * np + kk];
+      }
     }
   }
-  // eigenvalues on the diagonal; rank them (ascending for RR_GEN, descending for RR_SVD)
-  for (int i = tid; i < np; i += nt) lam[i] = (i < n_cur) ? Am[(size_t)i * np + i] : 0.0;
   __syncthreads();
-  int* rank_of = reinterpret_cast<int*>(csv);   // reuse: position -> original index
-  for (int i = tid; i < n_cur; i += nt) {
-    int rk = 0;
-    for (int j = 0; j < n_cur; ++j) {
-      const bool before = (A.mode == RR_GEN) ? (lam[j] < lam[i] || (lam[j] == lam[i] && j < i))
-                                             : (lam[j] > lam[i] || (lam[j] == lam[i] && j < i));
-      rk += before;
-    }
-    rank_of[rk] = i;
-  }
-  __syncthreads();
+  stamp(4);
   double* theta = vec + VS_THETA * KP;
   if (A.mode == RR_GEN) {
-    // C = D Z V[:, sel]  (n x nkeep, ld nkeep)
+    // C = D Z V[:, :nkeep]  (n x nkeep, ld nkeep); rows of dropped blocks are zero
     for (int idx = tid; idx < n * nkeep; idx += nt) {
       const int i = idx / nkeep, j = idx % nkeep;
-      if (i >= n_cur) {
+      if (i >= n_cur || j >= nwant) {
         Cm[(size_t)i * nkeep + j] = 0.0;
         continue;
       }
-      const int col = rank_of[j];
-      double s = 0.0;
-      for (int k = i; k < n_cur; ++k) s += G[(size_t)i * np + k] * Vm[(size_t)k * np + col];
-      Cm[(size_t)i * nkeep + j] = d[i] * s;
+      const double* vj = Zv + (size_t)j * np;
+      double sacc = 0.0;
+      for (int k = i; k < n_cur; ++k) sacc += G[(size_t)i * np + k] * vj[k];
+      Cm[(size_t)i * nkeep + j] = d[i] * sacc;
     }
-    for (int j = tid; j < nkeep; j += nt) theta[j] = lam[rank_of[j]];
+    for (int j = tid; j < nkeep; j += nt) theta[j] = j < nwant ? lam_s[j] : 0.0;
+    __syncthreads();
+    stamp(5);
   } else {
-    // C = V[:, sel] / sigma ; theta = sigma (descending)
+    // C = V[:, sel] / sigma with sigma = sqrt(eigenvalue), descending
     for (int idx = tid; idx < n * nkeep; idx += nt) {
       const int i = idx / nkeep, j = idx % nkeep;
-      const int col = rank_of[j];
-      const double sg = sqrt(fmax(lam[col], 0.0));
-      Cm[(size_t)i * nkeep + j] = sg > 0.0 ? Vm[(size_t)i * np + col] / sg : 0.0;
+      const int col = m_eig - 1 - j;
+      const double sg = (col >= 0) ? sqrt(fmax(lam_s[col], 0.0)) : 0.0;
+      Cm[(size_t)i * nkeep + j] = (col >= 0 && sg > 0.0) ? Zv[(size_t)col * np + i] / sg : 0.0;
     }
-    for (int j = tid; j < nkeep; j += nt) theta[j] = sqrt(fmax(lam[rank_of[j]], 0.0));
+    __syncthreads();
+    for (int j = tid; j < nkeep; j += nt) theta[j] = (m_eig - 1 - j >= 0) ? sqrt(fmax(lam_s[m_eig - 1 - j], 0.0)) : 0.0;
   }
 }
 
 // ---------------------------------------------------------------------------
 // rotation: out_o[:, j] = beta_o out_o[:, j] + alpha sum_{c in [c0_o, c1_o)} S[:, c] C[c, j]
 // ---------------------------------------------------------------------------
-constexpr int RT_ROWS = 64;
-constexpr int RT_CC = 16;
-constexpr int RT_MAXC = 96;   // max output columns
-constexpr int RT_PER = RT_MAXC / 4;
+constexpr int RT_ROWS = 64;   // 4 waves x 16 rows
+constexpr int RT_CC = 32;     // C rows staged per step
+constexpr int RT_MAXC = 96;   // max output columns (6 MFMA column tiles)
+constexpr int RT_NCT = RT_MAXC / 16;
 
+// out_o[:, j] = beta_o out_o[:, j] + alpha sum_c S[:, c] C[c, j] with FP64 MFMA.
+// With two outputs whose C row ranges nest (range 1 is a suffix of range 0),
+// the suffix is accumulated first, stored as output 1, then completed.
 template <typename T>
 __global__ void __launch_bounds__(256) k_rotate(RotArgs A) {
   const int e = blockIdx.y;
@@ -484,55 +594,60 @@ __global__ void __launch_bounds__(256) k_rotate(RotArgs A) {
     c0[o] = A.c_blockrows > 0 ? A.c0[o] * kS : A.c0[o];
     c1[o] = A.c_blockrows > 0 ? A.c1[o] * kS : A.c1[o];
   }
-  const int cmin = min(c0[0], A.nout > 1 ? c0[1] : c0[0]);
-  const int cmax = max(c1[0], A.nout > 1 ? c1[1] : c1[0]);
-  __shared__ double ss[RT_CC][RT_ROWS + 1];
-  __shared__ double sc[RT_CC][RT_MAXC];
-  const int row = threadIdx.x % RT_ROWS;
-  const int cg = threadIdx.x / RT_ROWS;   // 0..3, uniform per wave
-  double acc[2][RT_PER];
-#pragma unroll
-  for (int o = 0; o < 2; ++o)
-#pragma unroll
-    for (int q = 0; q < RT_PER; ++q) acc[o][q] = 0.0;
+  __shared__ double sc[RT_CC][RT_MAXC + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rbase = r0 + w * 16;
+  const int rA = rbase + (lane & 15);
+  const int kl = lane >> 4;
+  const int nct = (ncol + 15) / 16;
   const double* Cm = E.small + soff(A.c_off, E);
-  for (int cb = cmin; cb < cmax; cb += RT_CC) {
-    for (int idx = threadIdx.x; idx < RT_CC * RT_ROWS; idx += 256) {
-      const int cc = idx / RT_ROWS, rr = idx % RT_ROWS;
-      const int c = cb + cc, r = r0 + rr;
-      ss[cc][rr] = (c < cmax && r < nrows) ? double(vcol<T>(E, A.S, c, kS)[r]) : 0.0;
-    }
-    for (int idx = threadIdx.x; idx < RT_CC * RT_MAXC; idx += 256) {
-      const int cc = idx / RT_MAXC, j = idx % RT_MAXC;
-      const int c = cb + cc;
-      sc[cc][j] = (c < cmax && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
-    }
-    __syncthreads();
-    for (int cc = 0; cc < RT_CC; ++cc) {
-      const int c = cb + cc;
-      const double s = ss[cc][row];
-      const bool in0 = (c >= c0[0] && c < c1[0]);
-      const bool in1 = (A.nout > 1 && c >= c0[1] && c < c1[1]);
+  d4v acc[RT_NCT];
 #pragma unroll
-      for (int q = 0; q < RT_PER; ++q) {
-        const double cv = s * sc[cc][cg + 4 * q];
-        if (in0) acc[0][q] += cv;
-        if (in1) acc[1][q] += cv;
+  for (int t = 0; t < RT_NCT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+  const int nseg = A.nout > 1 ? 2 : 1;
+  for (int sg = 0; sg < nseg; ++sg) {
+    // segment bounds
+    int lo, hi;
+    if (A.nout > 1) {
+      lo = sg == 0 ? c0[1] : c0[0];
+      hi = sg == 0 ? c1[1] : c0[1];
+    } else {
+      lo = c0[0];
+      hi = c1[0];
+    }
+    for (int cb = lo; cb < hi; cb += RT_CC) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < RT_CC * RT_MAXC; idx += 256) {
+        const int cc = idx / RT_MAXC, j = idx % RT_MAXC;
+        const int c = cb + cc;
+        sc[cc][j] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 2
+      for (int ks = 0; ks < RT_CC / 4; ++ks) {
+        const int c = cb + ks * 4 + kl;
+        const double av = (c < hi && rA < nrows) ? double(vcol<T>(E, A.S, c, kS)[rA]) : 0.0;
+#pragma unroll
+        for (int t = 0; t < RT_NCT; ++t)
+          if (t < nct) acc[t] = mfma16x16x4(av, sc[ks * 4 + kl][t * 16 + (lane & 15)], acc[t]);
       }
     }
-    __syncthreads();
-  }
-  const int r = r0 + row;
-  if (r >= nrows) return;
-  for (int o = 0; o < A.nout; ++o) {
+    // store the output this segment completes
+    const int o = (A.nout > 1 && sg == 0) ? 1 : 0;
     T* out = reinterpret_cast<T*>(E.blk[A.out_blk[o]]);
 #pragma unroll
-    for (int q = 0; q < RT_PER; ++q) {
-      const int j = cg + 4 * q;
-      if (j < ncol) {
-        T* p = out + (size_t)j * E.ld + r;
-        const double prev = A.beta[o] != 0.0 ? A.beta[o] * double(*p) : 0.0;
-        *p = T(prev + A.alpha * acc[o][q]);
+    for (int t = 0; t < RT_NCT; ++t) {
+      if (t >= nct) continue;
+      const int j = t * 16 + (lane & 15);
+      if (j >= ncol) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = rbase + kl + 4 * q;
+        if (r < nrows) {
+          T* p = out + (size_t)j * E.ld + r;
+          const double prev = A.beta[o] != 0.0 ? A.beta[o] * double(*p) : 0.0;
+          *p = T(prev + A.alpha * acc[t][q]);
+        }
       }
     }
   }
@@ -752,7 +867,7 @@ static void max_dims(Ctx& c, int code, int* maxk, int* maxN, int* maxE) {
 }
 
 static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
-                     long long out_off, const int* active, int rows_e) {
+                     long long out_off, const int* active, int rows_e, int sym) {
   int ks, kt, maxN, maxE;
   max_dims(c, kS, &ks, &maxN, &maxE);
   max_dims(c, kT, &kt, &maxN, &maxE);
@@ -760,8 +875,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   const int rows = rows_e ? maxE : maxN;
   const int tiles = ((maxni + GT - 1) / GT) * ((maxnj + GT - 1) / GT);
   int nsplit = std::max(1, std::min(c.gram_max_split, (2048 + tiles * c.n_elem - 1) / (tiles * c.n_elem)));
-  nsplit = std::min(nsplit, std::max(1, rows / 1024));
-  GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, (maxnj + GT - 1) / GT, rows_e, c.gram_part,
+  nsplit = std::min(nsplit, std::max(1, rows / 2048));
+  GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, (maxnj + GT - 1) / GT, rows_e, sym, c.gram_part,
               c.gram_part_stride, c.gram_part_ld};
   double flops = 0.0;
   for (int e = 0; e < c.n_elem; ++e) {
@@ -775,7 +890,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   dim3 g1(tiles, nsplit, c.n_elem);
   if (prec == DG_FP64) hipLaunchKernelGGL(k_gram<double>, g1, dim3(256), 0, c.stream, ga);
   else hipLaunchKernelGGL(k_gram<float>, g1, dim3(256), 0, c.stream, ga);
-  GramReduceArgs ra{c.elems_dev, active, S.nb, T.nb, kS, kT, nsplit, c.gram_part,
+  GramReduceArgs ra{c.elems_dev, active, sym, S.nb, T.nb, kS, kT, nsplit, c.gram_part,
                     c.gram_part_stride, c.gram_part_ld, out_off, 0};
   dim3 g2((maxni * maxnj + 255) / 256, c.n_elem);
   hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, c.stream, ra);
@@ -784,19 +899,35 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
 }
 
 int launch_gram(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
-                long long out_off, const int* active) {
-  return gram_impl(c, prec, S, kS, T, kT, out_off, active, 0);
+                long long out_off, const int* active, int sym) {
+  return gram_impl(c, prec, S, kS, T, kT, out_off, active, 0, sym);
 }
 
 int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
-                     long long out_off, int rows_e) {
-  return gram_impl(c, prec, S, kS, T, kT, out_off, nullptr, rows_e);
+                     long long out_off, int rows_e, int sym) {
+  return gram_impl(c, prec, S, kS, T, kT, out_off, nullptr, rows_e, sym);
 }
 
 int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) {
-  RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status};
+  // largest matrix order over the elements decides the dynamic LDS size
+  int npmax = 0;
+  for (int e = 0; e < c.n_elem; ++e) {
+    const int n = mode == RR_GEN ? nb * c.K[e] : (kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
+    npmax = std::max(npmax, n + (n & 1));
+  }
+  const size_t lds_bytes = (size_t)npmax * npmax * sizeof(double);
+  // static LDS of k_rr is ~16.5 KB; 146,000 B of dynamic LDS keeps the total under 160 KB
+  const bool use_lds = lds_bytes <= 146000;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_rr, hipFuncAttributeMaxDynamicSharedMemorySize, 146000);
+    attr_set = true;
+  }
+  RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status, use_lds ? npmax : 0,
+           c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
+           c.rr_pivot_tol, c.rr_ortol};
   TimedScope ts(c, TC_RR);
-  hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), 0, c.stream, a);
+  hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

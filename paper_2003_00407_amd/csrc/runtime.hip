@@ -133,12 +133,13 @@ struct ElemPlan {
 
 struct Plan {
   std::vector<ElemPlan> el;
-  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres;
+  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres, off_phase;
   size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_lists;
   size_t off_ckpt, off_part;
   size_t ckpt_block_bytes;
   int n_ckpt;
   int part_ld, nsplit_max;
+  size_t part_stride;
   size_t total;
   std::vector<ProjPlan> proj;
 };
@@ -242,6 +243,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_active = take(sizeof(int) * n_elem);
   P.off_status = take(sizeof(int) * n_elem);
   P.off_count = take(sizeof(int) * 4);
+  P.off_phase = take(sizeof(long long) * 8 * n_elem);
   P.off_maxres = take(sizeof(double) * n_elem);
   P.off_offx0 = take(sizeof(long long) * (n_elem + 1));
   P.off_offvec = take(sizeof(long long) * (n_elem + 1));
@@ -278,7 +280,9 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.ckpt_block_bytes = ckpt_block;
   P.n_ckpt = max_cheb > 0 ? (max_cheb / stride + 2) : 0;
   P.off_ckpt = take(P.ckpt_block_bytes * P.n_ckpt + 256);
-  P.off_part = take(sizeof(double) * (size_t)n_elem * P.nsplit_max * P.part_ld * P.part_ld);
+  // split-N Gram partials; the same region is the Rayleigh-Ritz inverse-iteration workspace
+  P.part_stride = std::max((size_t)P.nsplit_max * P.part_ld * P.part_ld, (size_t)6 * (P.part_ld + 2) * 512);
+  P.off_part = take(sizeof(double) * (size_t)n_elem * P.part_stride);
   P.total = off + 256;
   return DG_OK;
 }
@@ -324,6 +328,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->max_cheb = opt ? std::max(0, opt->max_cheb_degree) : 0;
   c->ckpt_stride = opt ? std::max(1, opt->ckpt_stride) : 1;
   if (const char* lv = std::getenv("DG_LOG")) c->log_level = std::atoi(lv);
+  if (const char* ot = std::getenv("DG_RR_ORTOL")) c->rr_ortol = std::atof(ot);
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {
@@ -479,11 +484,12 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->dev_active = (int*)(A + P.off_active);
   c->dev_status = (int*)(A + P.off_status);
   c->dev_count = (int*)(A + P.off_count);
+  c->dev_phase = (long long*)(A + P.off_phase);
   c->dev_maxres = (double*)(A + P.off_maxres);
   c->gram_part_ld = P.part_ld;
   c->gram_max_split = P.nsplit_max;
   c->gram_part = (double*)(A + P.off_part);
-  c->gram_part_stride = (long long)P.nsplit_max * P.part_ld * P.part_ld;
+  c->gram_part_stride = (long long)P.part_stride;
   c->ckpt_base = A + P.off_ckpt;
   c->ckpt_bytes_per_block = P.ckpt_block_bytes;
   c->ckpt_off.assign(n_elem, 0);

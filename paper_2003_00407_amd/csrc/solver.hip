@@ -63,8 +63,9 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   int st;
   ColSet S{nb, {B_X, B_W, B_P}};
   ColSet HS{nb, {B_HX, B_HW, B_HP}};
-  if ((st = launch_gram(c, prec, S, KC_K, S, KC_K, small_code(0), active))) return st;
-  if ((st = launch_gram(c, prec, S, KC_K, HS, KC_K, small_code(1), active))) return st;
+  // S^T S and S^T H S are symmetric (the latter in exact arithmetic): upper tiles, mirrored
+  if ((st = launch_gram(c, prec, S, KC_K, S, KC_K, small_code(0), active, 1))) return st;
+  if ((st = launch_gram(c, prec, S, KC_K, HS, KC_K, small_code(1), active, 1))) return st;
   if ((st = launch_rr(c, nb, 0, 0, RR_GEN, active))) return st;
   // X' = S C (-> T0), P' = [W P] C_WP (-> T1); HX' = HS C, HP' = [HW HP] C_WP
   RotArgs ra{};
@@ -98,6 +99,10 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
 static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done) {
   int st;
   int* active = c.dev_active;
+  // an FP32 stage stops an element once its residual stops improving (FP32 floor)
+  const bool stagnation_exit = (prec != DG_FP64);
+  std::vector<double> best(c.n_elem, 1e300);
+  std::vector<int> stall(c.n_elem, 0);
   // start: H X, then Rayleigh-Ritz on span(X) (orthonormalises X, step 1)
   {
     std::vector<int> ones(c.n_elem, 1);
@@ -105,6 +110,8 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
   c.active_host.assign(c.n_elem, 1);
+  // Gram matrices of FP32 blocks are accurate to ~1e-7: treat smaller scaled pivots as breakdown
+  c.rr_pivot_tol = (prec == DG_FP64) ? 1e-13 : 1e-6;
   if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
   if ((st = rr_and_rotate(c, prec, 1, active, false))) return st;
   bool have_p = false;
@@ -124,6 +131,27 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
       if ((st = sync_read(c, act.data(), active, sizeof(int) * c.n_elem))) return st;
       for (int e = 0; e < c.n_elem; ++e)
         if (act[e] > 0) it_elem[e] = it;
+      if (stagnation_exit) {
+        std::vector<double> mr(c.n_elem);
+        if ((st = sync_read(c, mr.data(), c.dev_maxres, sizeof(double) * c.n_elem))) return st;
+        bool changed = false;
+        for (int e = 0; e < c.n_elem; ++e) {
+          if (act[e] <= 0) continue;
+          if (mr[e] < 0.8 * best[e]) {
+            best[e] = mr[e];
+            stall[e] = 0;
+          } else if (++stall[e] >= 6) {
+            act[e] = 0;
+            changed = true;
+            --cnt[0];
+          }
+        }
+        if (changed) {
+          c.host_ints = act;
+          DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice,
+                                c.stream));
+        }
+      }
       c.active_host = act;
     }
     if (c.log_level > 0) {
@@ -138,6 +166,17 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
         brk += stv[e] != 0;
       }
       fprintf(stderr, "[dg] lobpcg prec=%d it=%d active=%d max_res=%.3e rr_fallbacks=%d\n", prec, it, cnt[0], m, brk);
+      if (c.log_level >= 3) {
+        for (int e = 0; e < c.n_elem; ++e) fprintf(stderr, " %.1e/%d", mr[e], stv[e]);
+        fprintf(stderr, "\n");
+      }
+      if (c.log_level >= 2 && it % 10 == 1) {
+        std::vector<long long> ph(8 * c.n_elem);
+        if ((st = sync_read(c, ph.data(), c.dev_phase, sizeof(long long) * 8 * c.n_elem))) return st;
+        fprintf(stderr, "[dg] rr phases (us @100MHz): chol %.0f zinv %.0f matmul %.0f jacobi %.0f coeff %.0f\n",
+                (ph[1] - ph[0]) / 100.0, (ph[2] - ph[1]) / 100.0, (ph[3] - ph[2]) / 100.0,
+                (ph[4] - ph[3]) / 100.0, (ph[5] - ph[4]) / 100.0);
+      }
     }
     if (cnt[0] == 0) break;
     // W = T(HX - X Theta)  (Eq. (3), step 3)
@@ -145,7 +184,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     // W <- W - X (X^T W)
     {
       ColSet SX{1, {B_X, 0, 0}}, SW{1, {B_W, 0, 0}};
-      if ((st = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active))) return st;
+      if ((st = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active, 0))) return st;
       RotArgs ra{};
       ra.active = active;
       ra.S = SX;
@@ -266,7 +305,7 @@ int make_alb(Ctx& c, double* alb, double* sval) {
   const int X = B_X, t0 = B_T0, t1 = B_T1;
   if ((st = launch_gather_e(c, X, t0))) return st;
   ColSet S0{1, {t0, 0, 0}}, S1{1, {t1, 0, 0}};
-  if ((st = launch_gram_rows(c, DG_FP64, S0, KC_J, S0, KC_J, small_code(0), 1))) return st;
+  if ((st = launch_gram_rows(c, DG_FP64, S0, KC_J, S0, KC_J, small_code(0), 1, 1))) return st;
   if ((st = launch_rr(c, 0, KC_J, KC_J, RR_SVD, nullptr))) return st;
   if ((st = launch_extract_theta(c, sval))) return st;
   RotArgs ra{};
@@ -283,7 +322,7 @@ int make_alb(Ctx& c, double* alb, double* sval) {
   ra.rows_e = 1;
   if ((st = launch_rotate(c, DG_FP64, ra))) return st;
   // second pass restores orthonormality to working precision
-  if ((st = launch_gram_rows(c, DG_FP64, S1, KC_J, S1, KC_J, small_code(0), 1))) return st;
+  if ((st = launch_gram_rows(c, DG_FP64, S1, KC_J, S1, KC_J, small_code(0), 1, 1))) return st;
   if ((st = launch_rr(c, 0, KC_J, KC_J, RR_SVD, nullptr))) return st;
   ra.S = S1;
   ra.out_blk[0] = t0;

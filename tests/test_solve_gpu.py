@@ -111,3 +111,34 @@ def test_c2_full_size_certificate():
         print(f"c2 elem {k}: iters {iters[k]} max certificate residual {rn.max():.2e}")
         # each Ritz value lies within ||r_i|| of an eigenvalue of H
         assert rn.max() < 2e-8
+
+
+@pytest.mark.parametrize("J", [7, 19])
+def test_free_electron_shells_vs_golden(J):
+    """v = 0 in the 10 bohr cube: eigenvalues are the closed-form |G|^2/2 shells (degenerate)."""
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "free_electron_10bohr_16cubed.txt"))
+    expect = np.concatenate([np.full(int(m), v) for _, v, m, _ in rows])[:J]
+    el = W.free_electron_element(n_states=J)
+    E, eig, res, iters, st = _solve([el], seed_base=50 + J)
+    print(f"free electrons J={J}: iters {iters[0]} err {np.abs(eig[0] - expect).max():.2e}")
+    assert st == 0
+    assert np.max(np.abs(eig[0] - expect)) < EIG_TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c3_shape_certificate(precision):
+    """Two 48x48x64 elements with 60 states (projected problem 198 x 198), FP64 and mixed."""
+    torch = need_torch_cuda()
+    from paper_2003_00407_amd import dgalb as D
+    els = W.make_config("c3").elements[:2]
+    E, eig, res, iters, st = _solve(els, precision=precision, seed_base=3000, tol=1e-8)
+    assert st == 0
+    X = unpack(E.vectors().cpu().numpy(), E.offsets(D.DG_OFF_VEC), [e.npts for e in els],
+               [e.n_states for e in els])
+    for k, el in enumerate(els):
+        Xk = X[k]
+        assert np.max(np.abs(Xk.T @ Xk - np.eye(el.n_states))) < 1e-10
+        rn = np.linalg.norm(planewave.hpsi(el, Xk) - Xk * eig[k][None, :], axis=0)
+        print(f"c3 prec={precision} elem {k}: iters {iters[k]} max certificate residual {rn.max():.2e}")
+        assert rn.max() < 2e-8
