@@ -170,23 +170,31 @@ int32_t dg_make_alb(dg_ctx *ctx, double *alb_dev, double *sval_dev);
 
 /* Band energy E = sum_i f_i psi_i^T H psi_i with Psi = p_m(H) Psi_0, p_m the
  * degree-m scaled Chebyshev filter of Algorithm 2 / Eq. (8) with bounds
- * (a, b) and scale a0 per element (bounds_host: 3 values per element), for
- * n_vec columns per element.  psi0_dev: packed N_k x n_vec (FP64 for DG_FP64,
- * FP32 for DG_FP32); f_dev: n_vec FP64 weights per element (same for all);
- * E_dev: one FP64 energy per element.  Intermediates are checkpointed every
- * ckpt_stride steps for dg_band_energy_backward.  Errors: DG_ERR_ARG. */
+ * (a, b, a0) per element (bounds_host: 3 host values per element, a0 < a < b;
+ * the coefficients are held fixed, not differentiated), for n_vec columns per
+ * element.  psi0_dev: packed N_k x n_vec (FP64 for DG_FP64, FP32 for DG_FP32);
+ * f_dev: n_vec FP64 weights (device, same for every element, kept alive until
+ * the backward call); E_dev: one FP64 energy per element.  Every ckpt_stride-th
+ * pair of filter iterates is kept for dg_band_energy_backward.  The context
+ * must have been created with max_cheb_degree >= degree.  Overwrites the
+ * solver's blocks (call dg_solve_elements again before dg_make_alb).
+ * Errors: DG_ERR_ARG. */
 int32_t dg_band_energy(dg_ctx *ctx, int32_t prec, int32_t degree, const double *bounds_host,
                        int32_t n_vec, const void *psi0_dev, const double *f_dev, double *E_dev);
 
-/* Gradient of the last dg_band_energy call: dpsi0_dev = dE/dPsi_0 (packed
- * like psi0, scaled by dE_host[k] per element), dv_dev = dE/dV_eff (N_k per
- * element, DG_OFF_GRID, FP64 or FP32 as psi0).  Recomputes each checkpoint
- * segment.  Errors: DG_ERR_STATE without a preceding dg_band_energy. */
+/* Gradient of the last dg_band_energy call, scaled per element by dE_host[k]
+ * (the upstream gradient): dpsi0_dev = dE dE/dPsi_0 (packed like psi0, its
+ * precision) by the adjoint three-term recurrence, recomputing each
+ * checkpointed segment of the filter; dv_dev = dE dE/dV_eff (FP64, N_k per
+ * element, DG_OFF_GRID).  Errors: DG_ERR_STATE without a preceding
+ * dg_band_energy. */
 int32_t dg_band_energy_backward(dg_ctx *ctx, const double *dE_host, void *dpsi0_dev,
                                 void *dv_dev);
 
-/* Replace V_eff of every element (FP64, DG_OFF_GRID packed), e.g. for an inner
- * SCF step or for gradients with respect to V.  Errors: DG_ERR_ARG. */
+/* Replace V_eff of every element (v_dev: FP64 device buffer, packed N_k per
+ * element, DG_OFF_GRID), e.g. for an inner SCF step ("Generating ALB
+ * functions": the ALBs adapt as V_eff changes) or for finite differences in V.
+ * Invalidates previous eigenvectors.  Errors: DG_ERR_ARG. */
 int32_t dg_set_potential(dg_ctx *ctx, const double *v_dev);
 
 /* Per-kernel-class GPU time accumulated since the last reset, measured with

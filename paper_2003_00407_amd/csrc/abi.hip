@@ -126,9 +126,7 @@ int32_t dg_band_energy(dg_ctx* ctx, int32_t prec, int32_t degree, const double* 
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  (void)prec; (void)degree; (void)bounds_host; (void)n_vec; (void)psi0_dev; (void)f_dev; (void)E_dev;
-  dg::set_error("band energy not available in this build");
-  return DG_ERR_ARG;
+  DG_GUARD(return dg::band_energy(ctx->impl, prec, degree, bounds_host, n_vec, psi0_dev, f_dev, E_dev);)
 }
 
 int32_t dg_band_energy_backward(dg_ctx* ctx, const double* dE_host, void* dpsi0_dev, void* dv_dev) {
@@ -136,9 +134,7 @@ int32_t dg_band_energy_backward(dg_ctx* ctx, const double* dE_host, void* dpsi0_
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  (void)dE_host; (void)dpsi0_dev; (void)dv_dev;
-  dg::set_error("no band energy has been computed on this context");
-  return DG_ERR_STATE;
+  DG_GUARD(return dg::band_energy_backward(ctx->impl, dE_host, dpsi0_dev, dv_dev);)
 }
 
 int32_t dg_set_potential(dg_ctx* ctx, const double* v_dev) {
@@ -146,8 +142,7 @@ int32_t dg_set_potential(dg_ctx* ctx, const double* v_dev) {
     dg::set_error("ctx or v_dev is NULL");
     return DG_ERR_ARG;
   }
-  dg::set_error("dg_set_potential not available in this build");
-  return DG_ERR_ARG;
+  DG_GUARD(return dg::set_potential(ctx->impl, v_dev);)
 }
 
 int32_t dg_timing_work(dg_ctx* ctx, double* work_host) {

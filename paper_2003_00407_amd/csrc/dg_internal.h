@@ -11,7 +11,9 @@
 
 namespace dg {
 
-constexpr int kMaxBlocks = 8;   // logical N x K blocks per element
+constexpr int kMaxBlocks = 8;     // solver blocks per element (roles permuted per element)
+constexpr int kExtraBlocks = 40;  // band-energy checkpoint / segment blocks (allocated on demand)
+constexpr int kTotalBlocks = kMaxBlocks + kExtraBlocks;
 enum BlockId { B_X = 0, B_W = 1, B_P = 2, B_HX = 3, B_HW = 4, B_HP = 5, B_T0 = 6, B_T1 = 7 };
 
 // Per-element data resident on the device (read-only in kernels).
@@ -41,8 +43,10 @@ struct ElemDev {
   const int* ent_proj;     // projector ids, ascending per point
   const double* ent_val64;
   const float* ent_val32;
-  // per-element block bases (FP64 view; the FP32 view uses the same bytes)
-  void* blk[kMaxBlocks];
+  // per-element block bases (FP64 view; the FP32 view uses the same bytes);
+  // blocks kMaxBlocks.. exist only when the context was created for band energies
+  void* blk[kTotalBlocks];
+  double bup;              // upper bound of the spectrum of H^{Q_k} (Chebyshev filter)
   // per-element small-matrix workspace (FP64)
   double* small;           // see SmallLayout
   double* nlc;             // projector overlaps C = B^T X: nproj x Kmax3 (FP64)
@@ -122,6 +126,10 @@ struct Ctx {
   int* dev_status = nullptr;       // per element RR status
   int* dev_count = nullptr;        // [active count, NaN count]
   double* dev_maxres = nullptr;    // per element max residual
+  double* dev_bounds = nullptr;    // band energy: (a, b, a0) per element
+  double* dev_de = nullptr;        // band energy backward: dE per element
+  std::vector<double> be_bounds_host, be_de_host;
+  int n_extra_blocks = 0;
   long long* dev_off_x0 = nullptr; // packed offsets (doubles), per element
   long long* dev_off_vec = nullptr;
   long long* dev_off_alb = nullptr;
@@ -220,5 +228,9 @@ int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y);
 int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters);
 int get_vectors(Ctx& c, double* x);
 int make_alb(Ctx& c, double* alb, double* sval);
+int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_vec, const void* psi0,
+                const double* f, double* E);
+int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv);
+int set_potential(Ctx& c, const double* v);
 
 }  // namespace dg

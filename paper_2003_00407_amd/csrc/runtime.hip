@@ -126,14 +126,16 @@ struct ElemPlan {
   int J, G, K, Kpad, N, ld, kmax3, KP;
   size_t off_v64, off_v32, off_sptr, off_pbase, off_idx, off_val64, off_val32, off_vbase, off_gamma;
   size_t off_act_idx, off_act_ptr, off_ent_proj, off_ent_v64, off_ent_v32;
-  size_t off_blk[kMaxBlocks];
+  size_t off_blk[kTotalBlocks];
+  int n_blocks;
   size_t off_small, off_nlc;
   int ngrp, nact, nent;
 };
 
 struct Plan {
   std::vector<ElemPlan> el;
-  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres, off_phase;
+  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres, off_phase, off_bounds, off_de;
+  int n_extra;
   size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_lists;
   size_t off_ckpt, off_part;
   size_t ckpt_block_bytes;
@@ -230,6 +232,13 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
     kmax = std::max(kmax, p.K);
     build_proj_plan(d[e], p.N, P.proj[e]);
   }
+  // band energy: checkpoint pairs every ckpt_stride steps, Y_m, H Y_m, one segment
+  P.n_extra = max_cheb > 0 ? 2 * ((max_cheb + stride - 1) / stride) + 2 + stride : 0;
+  if (P.n_extra > kExtraBlocks) {
+    set_error("max_cheb_degree / ckpt_stride need " + std::to_string(P.n_extra) +
+              " checkpoint blocks (limit " + std::to_string(kExtraBlocks) + "); raise ckpt_stride");
+    return DG_ERR_ARG;
+  }
   P.part_ld = 3 * kmax;
   P.nsplit_max = std::max(1, std::min(16, 1024 / n_elem));
   size_t off = 0;
@@ -245,6 +254,8 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_count = take(sizeof(int) * 4);
   P.off_phase = take(sizeof(long long) * 8 * n_elem);
   P.off_maxres = take(sizeof(double) * n_elem);
+  P.off_bounds = take(sizeof(double) * 3 * n_elem);
+  P.off_de = take(sizeof(double) * n_elem);
   P.off_offx0 = take(sizeof(long long) * (n_elem + 1));
   P.off_offvec = take(sizeof(long long) * (n_elem + 1));
   P.off_offalb = take(sizeof(long long) * (n_elem + 1));
@@ -272,7 +283,8 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
     p.off_ent_proj = take(sizeof(int) * std::max<size_t>(1, pp.ent_proj.size()));
     p.off_ent_v64 = take(sizeof(double) * std::max<size_t>(1, pp.ent_val.size()));
     p.off_ent_v32 = take(sizeof(float) * std::max<size_t>(1, pp.ent_val.size()));
-    for (int b = 0; b < kMaxBlocks; ++b) p.off_blk[b] = take(sizeof(double) * (size_t)p.ld * p.Kpad);
+    p.n_blocks = kMaxBlocks + P.n_extra;
+    for (int b = 0; b < p.n_blocks; ++b) p.off_blk[b] = take(sizeof(double) * (size_t)p.ld * p.Kpad);
     p.off_small = take(sizeof(double) * SmallLayout::total(p.KP));
     p.off_nlc = take(sizeof(double) * (size_t)std::max(1, d[e].n_proj) * p.kmax3);
     ckpt_block += align256(sizeof(double) * (size_t)p.ld * p.Kpad);
@@ -377,9 +389,31 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
     E.kx = 0.5 * (tp / x.len[0]) * (tp / x.len[0]);
     E.ky = 0.5 * (tp / x.len[1]) * (tp / x.len[1]);
     E.kz = 0.5 * (tp / x.len[2]) * (tp / x.len[2]);
-    double vmin = x.v_eff[0];
-    for (int i = 0; i < p.N; ++i) vmin = std::min(vmin, x.v_eff[i]);
+    double vmin = x.v_eff[0], vmax = x.v_eff[0];
+    for (int i = 0; i < p.N; ++i) {
+      vmin = std::min(vmin, x.v_eff[i]);
+      vmax = std::max(vmax, x.v_eff[i]);
+    }
     E.vmin = vmin;
+    // Upper bound of the spectrum: max kinetic symbol + max V + a Gershgorin bound
+    // of sum_{gamma>0} gamma |b><b| through the projector overlaps |b_p . b_q|
+    {
+      const double kin = E.kx * (double)(x.n[0] / 2) * (x.n[0] / 2) + E.ky * (double)(x.n[1] / 2) * (x.n[1] / 2) +
+                         E.kz * (double)(x.n[2] / 2) * (x.n[2] / 2);
+      double nl = 0.0;
+      if (x.n_proj > 0) {
+        std::vector<double> rowsum(x.n_proj, 0.0);
+        for (size_t a2 = 0; a2 < pp.act_idx.size(); ++a2)
+          for (int q1 = pp.act_ptr[a2]; q1 < pp.act_ptr[a2 + 1]; ++q1)
+            for (int q2 = pp.act_ptr[a2]; q2 < pp.act_ptr[a2 + 1]; ++q2) {
+              const int p1 = pp.ent_proj[q1], p2 = pp.ent_proj[q2];
+              if (x.gamma[p1] > 0.0 && x.gamma[p2] > 0.0)
+                rowsum[p1] += std::sqrt(x.gamma[p1] * x.gamma[p2]) * std::fabs(pp.ent_val[q1] * pp.ent_val[q2]);
+            }
+        for (double r : rowsum) nl = std::max(nl, r);
+      }
+      E.bup = kin + std::max(vmax, 0.0) + nl + 1e-6;
+    }
     E.v64 = (const double*)(A + p.off_v64);
     E.v32 = (const float*)(A + p.off_v32);
     E.ngrp = p.ngrp;
@@ -397,7 +431,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
     E.ent_proj = (const int*)(A + p.off_ent_proj);
     E.ent_val64 = (const double*)(A + p.off_ent_v64);
     E.ent_val32 = (const float*)(A + p.off_ent_v32);
-    for (int b = 0; b < kMaxBlocks; ++b) E.blk[b] = A + p.off_blk[b];
+    for (int b = 0; b < kTotalBlocks; ++b) E.blk[b] = b < p.n_blocks ? A + p.off_blk[b] : nullptr;
     E.small = (double*)(A + p.off_small);
     E.nlc = (double*)(A + p.off_nlc);
     E.kmax3 = p.kmax3;
@@ -484,6 +518,9 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->dev_active = (int*)(A + P.off_active);
   c->dev_status = (int*)(A + P.off_status);
   c->dev_count = (int*)(A + P.off_count);
+  c->dev_bounds = (double*)(A + P.off_bounds);
+  c->dev_de = (double*)(A + P.off_de);
+  c->n_extra_blocks = P.n_extra;
   c->dev_phase = (long long*)(A + P.off_phase);
   c->dev_maxres = (double*)(A + P.off_maxres);
   c->gram_part_ld = P.part_ld;
@@ -504,7 +541,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   if ((st = cpy(P.off_elems, c->elems_host.data(), sizeof(ElemDev) * n_elem))) return st;
   // zero the blocks so padded columns and unused tails are defined
   for (int e = 0; e < n_elem; ++e)
-    for (int b = 0; b < kMaxBlocks; ++b) {
+    for (int b = 0; b < P.el[e].n_blocks; ++b) {
       hipError_t he = hipMemsetAsync(A + P.el[e].off_blk[b], 0, sizeof(double) * (size_t)P.el[e].ld * P.el[e].Kpad, s);
       if (he != hipSuccess) {
         set_error(std::string("hipMemsetAsync: ") + hipGetErrorString(he));

@@ -334,10 +334,3 @@ int make_alb(Ctx& c, double* alb, double* sval) {
 
 }  // namespace dg
 
-namespace dg {
-int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters, int* n_done) {
-  (void)c; (void)prec; (void)tol; (void)max_iter; (void)degree; (void)iters; (void)n_done;
-  set_error("Chebyshev-filtered solver not available in this build");
-  return DG_ERR_ARG;
-}
-}  // namespace dg

@@ -220,6 +220,38 @@ class Elements:
                "dg_make_alb")
         return alb, sv
 
+    def set_potential(self, v):
+        """Replace V_eff (packed FP64 CUDA tensor, N_k per element)."""
+        if v.dtype != self.torch.float64 or not v.is_cuda or not v.is_contiguous():
+            raise ValueError("v must be a contiguous CUDA float64 tensor")
+        _check(_lib.dg_set_potential(self.ctx, C.c_void_p(v.data_ptr())), "dg_set_potential")
+
+    def band_energy(self, psi0, f, degree: int, bounds, prec: int = DG_FP64):
+        """E per element for Psi = p_m(H) Psi_0 (packed psi0, n_vec columns per element)."""
+        torch = self.torch
+        n_vec = int(f.numel())
+        bnd = np.ascontiguousarray(np.asarray(bounds, dtype=np.float64).reshape(-1))
+        if bnd.size != 3 * self.n_elem:
+            raise ValueError("bounds needs 3 values per element")
+        E = self._dev(self.n_elem, torch.float64)
+        self._be_f = f          # must outlive the backward
+        _check(_lib.dg_band_energy(self.ctx, prec, degree, _ptr(bnd, C.c_double), n_vec,
+                                   C.c_void_p(psi0.data_ptr()), C.c_void_p(f.data_ptr()),
+                                   C.c_void_p(E.data_ptr())), "dg_band_energy")
+        self._be_shape = (psi0.numel(), psi0.dtype)
+        return E
+
+    def band_energy_backward(self, dE):
+        """(dE/dPsi_0 packed like psi0, dE/dV packed FP64) scaled by dE (per element)."""
+        torch = self.torch
+        n, dt = self._be_shape
+        dpsi = self._dev(n, dt)
+        dv = self._dev(int(self.offsets(DG_OFF_GRID)[-1]), torch.float64)
+        de = np.ascontiguousarray(np.asarray(dE, dtype=np.float64).reshape(-1))
+        _check(_lib.dg_band_energy_backward(self.ctx, _ptr(de, C.c_double), C.c_void_p(dpsi.data_ptr()),
+                                            C.c_void_p(dv.data_ptr())), "dg_band_energy_backward")
+        return dpsi, dv
+
     TIMING_CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
 
     def timing(self, enable: bool = True, reset: bool = False):
@@ -240,3 +272,38 @@ def pack_initial(elements: Sequence, seed_base: int, n_guard: int = -1):
         g = W.guard_count(el.n_states) if n_guard < 0 else n_guard
         parts.append(W.initial_block(el.npts, el.n_states + g, seed=seed_base + k).ravel())
     return np.concatenate(parts)
+
+
+def _band_energy_function():
+    import torch
+
+    class BandEnergy(torch.autograd.Function):
+        """E_k(V, Psi_0) = sum_i f_i psi_i^T H[V] psi_i through the degree-m Chebyshev filter.
+
+        forward(v, psi0, elements, f, degree, bounds, prec): v packed FP64 (N_k per
+        element) or None to keep the context's potential; psi0 packed (n_vec = f.numel()
+        columns per element).  Returns E (one FP64 value per element).  The backward
+        runs the checkpointed adjoint recurrence in the HIP library.
+        """
+
+        @staticmethod
+        def forward(ctx, v, psi0, elements, f, degree, bounds, prec=DG_FP64):
+            if v is not None:
+                elements.set_potential(v.detach().contiguous())
+            E = elements.band_energy(psi0.detach().contiguous(), f, degree, bounds, prec)
+            ctx.elements = elements
+            ctx.has_v = v is not None
+            return E
+
+        @staticmethod
+        def backward(ctx, gE):
+            dpsi, dv = ctx.elements.band_energy_backward(gE.detach().double().cpu().numpy())
+            return (dv if ctx.has_v else None), dpsi, None, None, None, None, None
+
+    return BandEnergy
+
+
+def __getattr__(name):
+    if name == "BandEnergy":
+        return _band_energy_function()
+    raise AttributeError(name)
