@@ -61,11 +61,19 @@ def run_path(E, D, x0, precision, steps, warmup, tol, torch):
 
 
 def kernel_table(r):
+    """Per kernel class: total ms, launches, average launch, achieved algorithmic rate."""
     tab = {}
     for i, name in enumerate(CLASSES):
         if r["launches"][i]:
-            tab[name] = {"ms_total": round(r["ms"][i], 3), "launches": int(r["launches"][i]),
-                         "avg_us": round(1000.0 * r["ms"][i] / r["launches"][i], 2)}
+            row = {"ms_total": round(r["ms"][i], 3), "launches": int(r["launches"][i]),
+                   "avg_us": round(1000.0 * r["ms"][i] / r["launches"][i], 2)}
+            if r["work"][i] > 0 and r["ms"][i] > 0:
+                rate = r["work"][i] / (r["ms"][i] / 1000.0)
+                if i <= 3:
+                    row["GBs"] = round(rate / 1e9, 1)
+                else:
+                    row["TFLOPs"] = round(rate / 1e12, 2)
+            tab[name] = row
     return tab
 
 

@@ -147,7 +147,7 @@ struct Ctx {
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable
   double rr_pivot_tol = 1e-13;     // overlap-Cholesky breakdown threshold (FP64 data)
-  double rr_ortol = 1e-3;          // cluster tolerance of the inverse iteration (relative to ||T||)
+  double rr_ortol = 1e-5;          // cluster tolerance of the inverse iteration (relative to ||T||)
   long long* dev_phase = nullptr;  // diagnostics: RR phase timestamps (8 per element)
 };
 

@@ -425,6 +425,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     se[m_eig - 1] = 0.0;
   }
   __syncthreads();
+  stamp(6);
   // (2) eigenvalues by bisection on Sturm counts (thread j -> j-th smallest)
   __shared__ double sb_lo, sb_hi, sb_norm;
   if (tid == 0) {
@@ -496,6 +497,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     }
     __syncthreads();
   }
+  stamp(7);
   // in-order modified Gram-Schmidt of the eigenvectors of T (one vector at a time,
   // the whole workgroup cooperating)
   for (int j = 1; j < nwant; ++j) {
