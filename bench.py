@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle LOBPCG iterations in the CPU sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy a buffer of this size once before timing (reference for PMC byte counters)")
     return ap.parse_args()
 
 
@@ -86,12 +88,12 @@ def roofline_for(r, prec_bytes):
     if i <= 3:       # HBM-bound passes: algorithmic bytes per launch / duration
         achieved = (w / n) / avg_s / 1e9
         peak, unit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
-    elif i <= 5:     # GEMMs: algorithmic flops per launch / duration (vector FMA path)
+    elif i <= 5:     # GEMMs on FP64 MFMA: algorithmic flops per launch / duration
         achieved = (w / n) / avg_s / 1e12
-        peak = FP64_PEAK_TFLOPS if prec_bytes == 8 else FP32_PEAK_TFLOPS
-        unit, bound = "TFLOP/s", "alu"
-    else:
-        achieved, peak, unit, bound = 0.0, FP64_PEAK_TFLOPS, "TFLOP/s", "alu"
+        peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "mfma"
+    else:            # small dense FP64 (one workgroup per element): vector ALU
+        achieved = (w / n) / avg_s / 1e12
+        peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "alu"
     return {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": None,
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": int(n)}
@@ -141,6 +143,11 @@ def main():
     els = cfg.elements
     E = D.Elements(els)
     x0 = torch.tensor(D.pack_initial(els, cfg.x0_seed_base), dtype=torch.float64, device="cuda")
+    if args.copy_probe_mib > 0:
+        buf = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        buf2 = torch.empty_like(buf)
+        buf2.copy_(buf)
+        del buf, buf2
     torch.cuda.synchronize()
     print(f"[bench] config={cfg.name} elements={len(els)} grid={els[0].n} J={els[0].n_states}",
           file=sys.stderr, flush=True)

@@ -925,10 +925,19 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
     hipFuncSetAttribute((const void*)k_rr, hipFuncAttributeMaxDynamicSharedMemorySize, 146000);
     attr_set = true;
   }
+  // algorithmic flop estimate: Cholesky + inverse (n^3/3 each), two n^3 products,
+  // tridiagonalisation (4n^3/3), back-transformation and coefficients (4 n^2 k)
+  double flops = 0.0;
+  for (int e = 0; e < c.n_elem; ++e) {
+    if (active && !c.active_host.empty() && !c.active_host[e]) continue;
+    const double n = mode == RR_GEN ? (double)nb * c.K[e] : (double)(kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
+    const double k = nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]);
+    flops += (mode == RR_GEN ? 2.0 / 3.0 + 2.0 : 0.0) * n * n * n + 4.0 / 3.0 * n * n * n + 4.0 * n * n * k;
+  }
   RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status, use_lds ? npmax : 0,
            c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
            c.rr_pivot_tol, c.rr_ortol};
-  TimedScope ts(c, TC_RR);
+  TimedScope ts(c, TC_RR, flops);
   hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
   DG_HIP(hipGetLastError());
   return DG_OK;
