@@ -128,6 +128,7 @@ struct Ctx {
   double* dev_maxres = nullptr;    // per element max residual
   double* dev_bounds = nullptr;    // band energy: (a, b, a0) per element
   double* dev_de = nullptr;        // band energy backward: dE per element
+  double* dev_minpiv = nullptr;    // diagnostics: smallest scaled overlap pivot of the last RR
   std::vector<double> be_bounds_host, be_de_host;
   int n_extra_blocks = 0;
   long long* dev_off_x0 = nullptr; // packed offsets (doubles), per element
@@ -147,6 +148,8 @@ struct Ctx {
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable
   double rr_pivot_tol = 1e-13;     // overlap-Cholesky breakdown threshold (FP64 data)
+  double rr_drop_tol = 1e-8;       // W/P columns with smaller scaled overlap pivots leave the basis
+  double rr_drop_env = -1.0;       // DG_RR_DROP override (diagnostics)
   double rr_ortol = 1e-5;          // cluster tolerance of the inverse iteration (relative to ||T||)
   long long* dev_phase = nullptr;  // diagnostics: RR phase timestamps (8 per element)
 };

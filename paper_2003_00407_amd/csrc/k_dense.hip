@@ -47,6 +47,13 @@ __device__ __forceinline__ const T* vcol(const ElemDev& E, const ColSet& s, int 
 
 // ---------------------------------------------------------------------------
 // Gram: part[e][split][i][j] = sum_{r in split} S[r,i] T[r,j]
+//
+// Row-panel design: a workgroup owns one element and one contiguous range of
+// grid rows, stages GP_R rows of EVERY column of S (and of T unless T == S)
+// in LDS per step, and accumulates the whole output (or the upper triangle,
+// for a symmetric result) in MFMA registers. Each input value is read from
+// HBM once per Gram; the partial sums of the row ranges are reduced in a
+// fixed order afterwards (deterministic).
 // ---------------------------------------------------------------------------
 struct GramArgs {
   const ElemDev* elems;
@@ -54,16 +61,19 @@ struct GramArgs {
   ColSet S, T;
   int kS, kT;          // columns per block (per element: <=0 -> E.K) -- multiplied by nb
   int nsplit;
-  int tiles_j;         // output tile columns of the launch grid
   int rows_e;          // 1: reduce over the first |E_k| rows only
-  int sym;             // 1: S == T, only tiles with ti <= tj are computed
+  int sym;             // 1: the result is symmetric, only 16x16 blocks with p <= q are computed
+  int same;            // 1: T is the same column set as S (staged once)
+  int cap;             // output blocks per workgroup (8 waves x MAXB)
   double* part;        // per element region of part_stride doubles
   long long part_stride;
-  int part_ld;         // leading dim of a partial tile matrix
+  int part_ld;         // leading dim of a partial matrix
 };
 
-constexpr int GT = 32;   // Gram output tile (4 waves x 16x16 MFMA sub-tiles)
-constexpr int GR = 64;   // rows staged per step
+constexpr int GP_THREADS = 512;
+constexpr int GP_R = 16;        // grid rows staged per step
+constexpr int GP_MAXCOL = 576;  // staged columns (S and T, padded to 16) per workgroup
+constexpr int GP_PF = GP_MAXCOL / (GP_THREADS / GP_R);   // staged values per thread and step
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
@@ -73,62 +83,114 @@ __device__ __forceinline__ d4v mfma16x16x4(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_gram(GramArgs A) {
+// 16x16 output block number b -> (p, q): row-major over p <= q when sym, else over all
+__device__ __forceinline__ void gram_block(int b, int bi, int bj, int sym, int& p, int& q) {
+  if (!sym) {
+    p = b / bj;
+    q = b - p * bj;
+    return;
+  }
+  p = 0;
+  while (b >= bj - p) {
+    b -= bj - p;
+    ++p;
+  }
+  q = p + b;
+}
+
+template <typename T, int MAXB>
+__global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
   const int e = blockIdx.z;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
   const int kS = kcode(A.kS, E);
   const int kT = kcode(A.kT, E);
   const int ni = A.S.nb * kS, nj = A.T.nb * kT;
-  const int ti = blockIdx.x / A.tiles_j, tj = blockIdx.x % A.tiles_j;
-  if (ti * GT >= ni || tj * GT >= nj) return;
-  if (A.sym && ti > tj) return;          // symmetric product: upper tiles only
+  const int bi = (ni + 15) >> 4, bj = (nj + 15) >> 4;
+  const int nblk = A.sym ? bi * (bi + 1) / 2 : bi * bj;
+  const int b0 = blockIdx.x * A.cap;
+  if (b0 >= nblk) return;
   const int split = blockIdx.y;
   const int nrows = nrows_of(E, A.rows_e);
-  const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GR - 1) / GR * GR;
+  const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GP_R - 1) / GP_R * GP_R;
   const int r0 = split * rows_per;
   const int r1 = min(nrows, r0 + rows_per);
-  __shared__ double sa[GR][GT + 1];
-  __shared__ double sb[GR][GT + 1];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wi = w & 1, wj = w >> 1;
-  // each thread stages 8 values per matrix: column idx/GR, row idx%GR (coalesced along rows)
-  const T* colA[8];
-  const T* colB[8];
-  int lrow[8], lcol[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int idx = threadIdx.x + 256 * q;
-    lcol[q] = idx / GR;
-    lrow[q] = idx % GR;
-    const int ci = ti * GT + lcol[q], cj = tj * GT + lcol[q];
-    colA[q] = ci < ni ? vcol<T>(E, A.S, ci, kS) : nullptr;
-    colB[q] = cj < nj ? vcol<T>(E, A.T, cj, kT) : nullptr;
+  const int ncS = bi * 16, nc = ncS + (A.same ? 0 : bj * 16);
+  const int toff = A.same ? 0 : ncS;      // LDS column of T's first column
+  const int pitch = nc + 1;
+  extern __shared__ double gsm[];
+  double* sm = gsm;                                       // [GP_R][pitch]
+  const T** cp = reinterpret_cast<const T**>(gsm + GP_R * pitch);   // [nc]
+  for (int c = threadIdx.x; c < nc; c += GP_THREADS) {
+    const T* ptr = nullptr;
+    if (c < ncS) {
+      if (c < ni) ptr = vcol<T>(E, A.S, c, kS);
+    } else if (c - ncS < nj) {
+      ptr = vcol<T>(E, A.T, c - ncS, kT);
+    }
+    cp[c] = ptr;
   }
-  d4v acc = {0.0, 0.0, 0.0, 0.0};
-  for (int r = r0; r < r1; r += GR) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // this wave's output blocks: b0 + w + 8 t
+  int bp[MAXB], bq[MAXB];
+  bool bv[MAXB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int rr = r + lrow[q];
-      sa[lrow[q]][lcol[q]] = (colA[q] && rr < r1) ? double(colA[q][rr]) : 0.0;
-      sb[lrow[q]][lcol[q]] = (colB[q] && rr < r1) ? double(colB[q][rr]) : 0.0;
+  for (int t = 0; t < MAXB; ++t) {
+    const int b = b0 + w + 8 * t;
+    bv[t] = b < nblk && b < b0 + A.cap;
+    int p = 0, q = 0;
+    if (bv[t]) gram_block(b, bi, bj, A.sym, p, q);
+    bp[t] = p * 16 + (lane & 15);
+    bq[t] = toff + q * 16 + (lane & 15);
+  }
+  d4v acc[MAXB];
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  // staging map: thread -> grid row (tid % 16) of columns tid / 16 + 32 u
+  const int srow = threadIdx.x & (GP_R - 1), scol = threadIdx.x >> 4;
+  double pre[GP_PF];
+  auto load = [&](int rbase) {
+    const int rr = rbase + srow;
+#pragma unroll
+    for (int u = 0; u < GP_PF; ++u) {
+      const int c = scol + 32 * u;
+      double v = 0.0;
+      if (c < nc) {
+        const T* ptr = cp[c];
+        if (ptr && rr < r1) v = double(ptr[rr]);
+      }
+      pre[u] = v;
     }
+  };
+  if (r0 < r1) load(r0);
+  for (int r = r0; r < r1; r += GP_R) {
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < GR / 4; ++ks) {
-      const double av = sa[ks * 4 + (lane >> 4)][wi * 16 + (lane & 15)];
-      const double bv = sb[ks * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
-      acc = mfma16x16x4(av, bv, acc);
+    for (int u = 0; u < GP_PF; ++u) {
+      const int c = scol + 32 * u;
+      if (c < nc) sm[srow * pitch + c] = pre[u];
     }
     __syncthreads();
+    if (r + GP_R < r1) load(r + GP_R);
+#pragma unroll
+    for (int ks = 0; ks < GP_R / 4; ++ks) {
+      const int rowoff = (ks * 4 + (lane >> 4)) * pitch;
+#pragma unroll
+      for (int t = 0; t < MAXB; ++t)
+        if (bv[t]) acc[t] = mfma16x16x4(sm[rowoff + bp[t]], sm[rowoff + bq[t]], acc[t]);
+    }
   }
   double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
-  const int j = tj * GT + wj * 16 + (lane & 15);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = ti * GT + wi * 16 + (lane >> 4) + 4 * q;
-    if (i < ni && j < nj) out[(size_t)i * A.part_ld + j] = acc[q];
+  for (int t = 0; t < MAXB; ++t) {
+    if (!bv[t]) continue;
+    const int i0 = bp[t] - (lane & 15), j = bq[t] - toff;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + (lane >> 4) + 4 * q;
+      if (i < ni && j < nj) out[(size_t)i * A.part_ld + j] = acc[t][q];
+    }
   }
 }
 
@@ -156,7 +218,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(GramReduceArgs A) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= ni * nj) return;
   const int i = idx / nj, j = idx % nj;
-  const bool mirror = A.sym && (i / GT) > (j / GT);
+  const bool mirror = A.sym && (i >> 4) > (j >> 4);
   const double* p = A.part + (size_t)e * A.part_stride +
                     (mirror ? (size_t)j * A.part_ld + i : (size_t)i * A.part_ld + j);
   double s = 0.0;
@@ -215,7 +277,9 @@ struct RRArgs {
   long long* phase_clk;  // optional: 8 timestamps per element (diagnostics)
   double* work;          // per element work region (inverse iteration)
   long long work_stride;
-  double pivot_tol;      // overlap Cholesky pivots below this (after unit-diagonal scaling) = breakdown
+  double pivot_tol;      // X-column overlap pivots below this (after unit-diagonal scaling) = breakdown
+  double drop_tol;       // W/P columns whose scaled pivot is below this are left out of the basis
+  double* minpiv;        // optional: smallest scaled pivot, its column, dropped count (diagnostics)
   double ortol;          // eigenvalues closer than ortol * ||T|| are treated as one cluster
 };
 
@@ -246,10 +310,13 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
   };
   stamp(0);
   // Inputs: G and A (n x n, ld n) as written by the Gram reduction.  For the
-  // generalised problem the leading blocks of S are tried in turn when the
-  // overlap Cholesky breaks down: [X W P], then [X W], then [X]; the
-  // coefficients of dropped blocks are zero (restart without P).
+  // generalised problem the overlap Cholesky runs over the columns of
+  // S = [X W P] in order; a W or P column whose remaining (scaled) pivot is
+  // below drop_tol is numerically in the span of the columns before it and is
+  // left out of the basis (its coefficients are zero), which keeps the
+  // projected problem well conditioned. A breakdown inside X itself keeps X.
   int n_cur = n;
+  int n_dropped = 0;
   if (A.mode == RR_GEN) {
     int attempt = 0;
     for (;;) {
@@ -265,7 +332,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
       __syncthreads();
       for (int i = tid; i < np; i += nt) {
         const double gii = Um[(size_t)i * np + i];
-        if (!(gii > 0.0)) brk = 1;
+        if (!(gii > 0.0) && i < K) brk = 1;
         d[i] = (i < m && gii > 0.0) ? 1.0 / sqrt(gii) : (i < m ? 0.0 : 1.0);
       }
       __syncthreads();
@@ -276,8 +343,33 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
       }
       __syncthreads();
       // Cholesky (upper, in place in Um): Um = U^T U
+      double pmin = 1.0;
+      int jmin = -1, ndrop = 0;
       for (int j = 0; j < m; ++j) {
         const double piv = Um[(size_t)j * np + j];
+        if (piv < pmin) {
+          pmin = piv;
+          jmin = j;
+        }
+        if (A.mode == RR_GEN && j >= K && !(piv > A.drop_tol)) {
+          // leave column j out: unit row and column in U, zero row and column in A
+          __syncthreads();
+          for (int i = tid; i < np; i += nt) {
+            if (i == j) continue;
+            Um[(size_t)i * np + j] = 0.0;
+            Um[(size_t)j * np + i] = 0.0;
+            Vm[(size_t)i * np + j] = 0.0;
+            Vm[(size_t)j * np + i] = 0.0;
+          }
+          if (tid == 0) {
+            Um[(size_t)j * np + j] = 1.0;
+            Vm[(size_t)j * np + j] = 0.0;
+            d[j] = 0.0;
+          }
+          ++ndrop;
+          __syncthreads();
+          continue;
+        }
         if (!(piv > A.pivot_tol) && tid == 0) brk = 1;
         const double ujj = sqrt(fmax(piv, 1e-300));
         __syncthreads();
@@ -291,11 +383,15 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
         }
         __syncthreads();
       }
+      if (A.minpiv && tid == 0 && attempt == 0) {
+        A.minpiv[3 * e] = pmin;
+        A.minpiv[3 * e + 1] = jmin;
+        A.minpiv[3 * e + 2] = ndrop;
+      }
+      n_dropped = ndrop;
       if (!brk) break;
       ++attempt;
-      if (n_cur > K) {
-        n_cur -= K;
-      } else {
+      {
         // unrecoverable: keep X (C = [I; 0; 0]) and report the status
         for (int idx = tid; idx < n * nkeep; idx += nt) {
           const int i = idx / nkeep, j = idx % nkeep;
@@ -346,6 +442,19 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
     for (int idx = tid; idx < np * np; idx += nt) {
       const int i = idx / np, j = idx % np;
       Am[idx] = (i < n_cur && j < n_cur) ? 0.5 * (Um[idx] + Um[(size_t)j * np + i]) : 0.0;
+    }
+    if (n_dropped > 0) {
+      // left-out columns get an eigenvalue above the whole spectrum (Gershgorin bound)
+      __syncthreads();
+      double rmax = 0.0;
+      for (int i = tid; i < n_cur; i += nt) {
+        double sacc = 0.0;
+        for (int k = 0; k < n_cur; ++k) sacc += fabs(Am[(size_t)i * np + k]);
+        rmax = fmax(rmax, sacc);
+      }
+      rmax = block_max(rmax, sh);
+      for (int j = tid; j < n_cur; j += nt)
+        if (d[j] == 0.0) Am[(size_t)j * np + j] = 2.0 * rmax + 1.0;
     }
   } else {
     // RR_SVD: eigen-decomposition of the Gram matrix itself
@@ -868,6 +977,10 @@ static void max_dims(Ctx& c, int code, int* maxk, int* maxN, int* maxE) {
   }
 }
 
+static bool set_lds_limit(const void* fn, int bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+}
+
 static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                      long long out_off, const int* active, int rows_e, int sym) {
   int ks, kt, maxN, maxE;
@@ -875,10 +988,27 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   max_dims(c, kT, &kt, &maxN, &maxE);
   const int maxni = S.nb * ks, maxnj = T.nb * kt;
   const int rows = rows_e ? maxE : maxN;
-  const int tiles = ((maxni + GT - 1) / GT) * ((maxnj + GT - 1) / GT);
-  int nsplit = std::max(1, std::min(c.gram_max_split, (2048 + tiles * c.n_elem - 1) / (tiles * c.n_elem)));
-  nsplit = std::min(nsplit, std::max(1, rows / 2048));
-  GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, (maxnj + GT - 1) / GT, rows_e, sym, c.gram_part,
+  const bool same = S.nb == T.nb && kS == kT &&
+                    std::equal(S.blk, S.blk + S.nb, T.blk);
+  if (sym && maxni != maxnj) { set_error("symmetric Gram of a non-square shape"); return DG_ERR_ARG; }
+  const int bi = (maxni + 15) / 16, bj = (maxnj + 15) / 16;
+  const int nc = bi * 16 + (same ? 0 : bj * 16);
+  if (nc > GP_MAXCOL) { set_error("Gram: more columns than one workgroup stages"); return DG_ERR_SHAPE; }
+  const int nblk = sym ? bi * (bi + 1) / 2 : bi * bj;
+  // output blocks per wave: the smallest instantiated count that covers the result,
+  // else 8 (larger results take several workgroups, each re-reading the columns)
+  static const int kMaxbList[] = {1, 2, 3, 4, 6, 8};
+  int maxb = 8;
+  for (int m : kMaxbList)
+    if (8 * m >= nblk) {
+      maxb = m;
+      break;
+    }
+  const int cap = 8 * maxb;
+  const int groups = (nblk + cap - 1) / cap;
+  int nsplit = std::max(1, std::min(c.gram_max_split, (1024 + groups * c.n_elem - 1) / (groups * c.n_elem)));
+  nsplit = std::min(nsplit, std::max(1, rows / 256));
+  GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, rows_e, sym, same ? 1 : 0, cap, c.gram_part,
               c.gram_part_stride, c.gram_part_ld};
   double flops = 0.0;
   for (int e = 0; e < c.n_elem; ++e) {
@@ -888,10 +1018,33 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     const double r = rows_e ? (double)c.en[0][e] * c.en[1][e] * c.en[2][e] : (double)c.N[e];
     flops += 2.0 * r * (S.nb * ke) * (T.nb * kt);
   }
+  const size_t lds = (size_t)GP_R * (nc + 1) * sizeof(double) + (size_t)nc * sizeof(void*);
   TimedScope ts(c, TC_GRAM, flops);
-  dim3 g1(tiles, nsplit, c.n_elem);
-  if (prec == DG_FP64) hipLaunchKernelGGL(k_gram<double>, g1, dim3(256), 0, c.stream, ga);
-  else hipLaunchKernelGGL(k_gram<float>, g1, dim3(256), 0, c.stream, ga);
+  dim3 g1(groups, nsplit, c.n_elem);
+#define DG_GRAM_CASE(MB)                                                                   \
+  case MB:                                                                                 \
+    if (prec == DG_FP64) {                                                                 \
+      static const bool attr = set_lds_limit((const void*)k_gram<double, MB>, 96000);      \
+      (void)attr;                                                                          \
+      hipLaunchKernelGGL((k_gram<double, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);   \
+    } else {                                                                               \
+      static const bool attr = set_lds_limit((const void*)k_gram<float, MB>, 96000);       \
+      (void)attr;                                                                          \
+      hipLaunchKernelGGL((k_gram<float, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);    \
+    }                                                                                      \
+    break;
+  switch (maxb) {
+    DG_GRAM_CASE(1)
+    DG_GRAM_CASE(2)
+    DG_GRAM_CASE(3)
+    DG_GRAM_CASE(4)
+    DG_GRAM_CASE(6)
+    DG_GRAM_CASE(8)
+    default:
+      set_error("Gram: unsupported block count");
+      return DG_ERR_SHAPE;
+  }
+#undef DG_GRAM_CASE
   GramReduceArgs ra{c.elems_dev, active, sym, S.nb, T.nb, kS, kT, nsplit, c.gram_part,
                     c.gram_part_stride, c.gram_part_ld, out_off, 0};
   dim3 g2((maxni * maxnj + 255) / 256, c.n_elem);
@@ -936,7 +1089,7 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
   }
   RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status, use_lds ? npmax : 0,
            c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
-           c.rr_pivot_tol, c.rr_ortol};
+           c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol};
   TimedScope ts(c, TC_RR, flops);
   hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
   DG_HIP(hipGetLastError());

@@ -134,7 +134,8 @@ struct ElemPlan {
 
 struct Plan {
   std::vector<ElemPlan> el;
-  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres, off_phase, off_bounds, off_de;
+  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres, off_phase, off_bounds, off_de,
+      off_minpiv;
   int n_extra;
   size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_lists;
   size_t off_ckpt, off_part;
@@ -240,7 +241,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
     return DG_ERR_ARG;
   }
   P.part_ld = 3 * kmax;
-  P.nsplit_max = std::max(1, std::min(16, 1024 / n_elem));
+  P.nsplit_max = std::max(1, std::min(64, 2048 / n_elem));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -256,6 +257,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_maxres = take(sizeof(double) * n_elem);
   P.off_bounds = take(sizeof(double) * 3 * n_elem);
   P.off_de = take(sizeof(double) * n_elem);
+  P.off_minpiv = take(3 * sizeof(double) * n_elem);
   P.off_offx0 = take(sizeof(long long) * (n_elem + 1));
   P.off_offvec = take(sizeof(long long) * (n_elem + 1));
   P.off_offalb = take(sizeof(long long) * (n_elem + 1));
@@ -341,6 +343,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->ckpt_stride = opt ? std::max(1, opt->ckpt_stride) : 1;
   if (const char* lv = std::getenv("DG_LOG")) c->log_level = std::atoi(lv);
   if (const char* ot = std::getenv("DG_RR_ORTOL")) c->rr_ortol = std::atof(ot);
+  if (const char* dt = std::getenv("DG_RR_DROP")) c->rr_drop_env = std::atof(dt);
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {
@@ -520,6 +523,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->dev_count = (int*)(A + P.off_count);
   c->dev_bounds = (double*)(A + P.off_bounds);
   c->dev_de = (double*)(A + P.off_de);
+  c->dev_minpiv = (double*)(A + P.off_minpiv);
   c->n_extra_blocks = P.n_extra;
   c->dev_phase = (long long*)(A + P.off_phase);
   c->dev_maxres = (double*)(A + P.off_maxres);

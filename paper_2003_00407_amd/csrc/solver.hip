@@ -86,11 +86,15 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   ra.ncol = KC_K;
   ra.c_blockrows = 1;
   if ((st = launch_rotate(c, prec, ra))) return st;
-  // X, P are free now: write HX', HP' there
+  // X, P are free now: HX' = HS C goes to X; HP' = H P' is applied afresh into P,
+  // so that S^T H S stays consistent with S in the nearly dependent directions
+  // of P (a rotated HP drifts from H P there)
+  const bool fresh_hp = ra.nout == 2;
   ra.S = HS;
+  ra.nout = 1;
   ra.out_blk[0] = B_X;
-  ra.out_blk[1] = B_P;
   if ((st = launch_rotate(c, prec, ra))) return st;
+  if (fresh_hp && (st = launch_hpsi(c, -1, 0, prec, B_T1, B_P, active))) return st;
   // new X = T0, P = T1, HX = X, HP = P, T0 = HX, T1 = HP
   int perm[kMaxBlocks] = {B_T0, B_W, B_T1, B_X, B_HW, B_P, B_HX, B_HP};
   return launch_permute(c, perm, active);
@@ -110,8 +114,11 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
   c.active_host.assign(c.n_elem, 1);
-  // Gram matrices of FP32 blocks are accurate to ~1e-7: treat smaller scaled pivots as breakdown
+  // Gram matrices of FP32 blocks are accurate to ~1e-7: treat smaller scaled pivots as breakdown.
+  // W/P columns whose scaled pivot is below drop_tol leave the basis: the projected
+  // matrix is then accurate to about eps * ||H|| / drop_tol in the worst kept direction.
   c.rr_pivot_tol = (prec == DG_FP64) ? 1e-13 : 1e-6;
+  c.rr_drop_tol = c.rr_drop_env >= 0.0 ? c.rr_drop_env : (prec == DG_FP64 ? 1e-8 : 1e-4);
   if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
   if ((st = rr_and_rotate(c, prec, 1, active, false))) return st;
   bool have_p = false;
@@ -167,7 +174,10 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
       }
       fprintf(stderr, "[dg] lobpcg prec=%d it=%d active=%d max_res=%.3e rr_fallbacks=%d\n", prec, it, cnt[0], m, brk);
       if (c.log_level >= 3) {
-        for (int e = 0; e < c.n_elem; ++e) fprintf(stderr, " %.1e/%d", mr[e], stv[e]);
+        std::vector<double> pv(3 * c.n_elem);
+        if ((st = sync_read(c, pv.data(), c.dev_minpiv, 3 * sizeof(double) * c.n_elem))) return st;
+        for (int e = 0; e < c.n_elem; ++e)
+          fprintf(stderr, " %.1e/%d/%.0e@%d-%d", mr[e], stv[e], pv[3 * e], (int)pv[3 * e + 1], (int)pv[3 * e + 2]);
         fprintf(stderr, "\n");
       }
       if (c.log_level >= 2 && it % 10 == 1) {
