@@ -681,16 +681,20 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
 // ---------------------------------------------------------------------------
 // rotation: out_o[:, j] = beta_o out_o[:, j] + alpha sum_{c in [c0_o, c1_o)} S[:, c] C[c, j]
 // ---------------------------------------------------------------------------
-constexpr int RT_ROWS = 64;   // 4 waves x 16 rows
+constexpr int RT_THREADS = 512;
+constexpr int RT_RT = 2;                            // 16-row tiles per wave
+constexpr int RT_ROWS = (RT_THREADS / 64) * RT_RT * 16;   // rows per workgroup (256)
 constexpr int RT_CC = 32;     // C rows staged per step
 constexpr int RT_MAXC = 96;   // max output columns (6 MFMA column tiles)
 constexpr int RT_NCT = RT_MAXC / 16;
 
 // out_o[:, j] = beta_o out_o[:, j] + alpha sum_c S[:, c] C[c, j] with FP64 MFMA.
+// The product is formed transposed, out^T = C^T S^T, so that each lane's
+// results are 16 consecutive grid rows of one column (128-byte stores).
 // With two outputs whose C row ranges nest (range 1 is a suffix of range 0),
 // the suffix is accumulated first, stored as output 1, then completed.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rotate(RotArgs A) {
+__global__ void __launch_bounds__(RT_THREADS) k_rotate(RotArgs A) {
   const int e = blockIdx.y;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
@@ -707,14 +711,17 @@ __global__ void __launch_bounds__(256) k_rotate(RotArgs A) {
   }
   __shared__ double sc[RT_CC][RT_MAXC + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int rbase = r0 + w * 16;
-  const int rA = rbase + (lane & 15);
   const int kl = lane >> 4;
+  int rrow[RT_RT];
+#pragma unroll
+  for (int u = 0; u < RT_RT; ++u) rrow[u] = r0 + (w * RT_RT + u) * 16 + (lane & 15);
   const int nct = (ncol + 15) / 16;
   const double* Cm = E.small + soff(A.c_off, E);
-  d4v acc[RT_NCT];
+  d4v acc[RT_RT][RT_NCT];
 #pragma unroll
-  for (int t = 0; t < RT_NCT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < RT_RT; ++u)
+#pragma unroll
+    for (int t = 0; t < RT_NCT; ++t) acc[u][t] = d4v{0.0, 0.0, 0.0, 0.0};
   const int nseg = A.nout > 1 ? 2 : 1;
   for (int sg = 0; sg < nseg; ++sg) {
     // segment bounds
@@ -726,38 +733,58 @@ __global__ void __launch_bounds__(256) k_rotate(RotArgs A) {
       lo = c0[0];
       hi = c1[0];
     }
+    // S values of the next C chunk are loaded while the current one is multiplied
+    double av[RT_CC / 4][RT_RT], an[RT_CC / 4][RT_RT];
+    auto load_s = [&](int cb, double (&dst)[RT_CC / 4][RT_RT]) {
+#pragma unroll
+      for (int ks = 0; ks < RT_CC / 4; ++ks) {
+        const int c = cb + ks * 4 + kl;
+        const T* col = c < hi ? vcol<T>(E, A.S, c, kS) : nullptr;
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) dst[ks][u] = (col && rrow[u] < nrows) ? double(col[rrow[u]]) : 0.0;
+      }
+    };
+    if (lo < hi) load_s(lo, an);
     for (int cb = lo; cb < hi; cb += RT_CC) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < RT_CC * RT_MAXC; idx += 256) {
+      for (int idx = threadIdx.x; idx < RT_CC * RT_MAXC; idx += RT_THREADS) {
         const int cc = idx / RT_MAXC, j = idx % RT_MAXC;
         const int c = cb + cc;
         sc[cc][j] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
       }
-      __syncthreads();
-#pragma unroll 2
-      for (int ks = 0; ks < RT_CC / 4; ++ks) {
-        const int c = cb + ks * 4 + kl;
-        const double av = (c < hi && rA < nrows) ? double(vcol<T>(E, A.S, c, kS)[rA]) : 0.0;
 #pragma unroll
-        for (int t = 0; t < RT_NCT; ++t)
-          if (t < nct) acc[t] = mfma16x16x4(av, sc[ks * 4 + kl][t * 16 + (lane & 15)], acc[t]);
+      for (int ks = 0; ks < RT_CC / 4; ++ks)
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) av[ks][u] = an[ks][u];
+      __syncthreads();
+      if (cb + RT_CC < hi) load_s(cb + RT_CC, an);
+#pragma unroll
+      for (int ks = 0; ks < RT_CC / 4; ++ks) {
+#pragma unroll
+        for (int t = 0; t < RT_NCT; ++t) {
+          if (t >= nct) continue;
+          const double cv = sc[ks * 4 + kl][t * 16 + (lane & 15)];
+#pragma unroll
+          for (int u = 0; u < RT_RT; ++u) acc[u][t] = mfma16x16x4(cv, av[ks][u], acc[u][t]);
+        }
       }
     }
-    // store the output this segment completes
+    // store the output this segment completes: lane holds out[row rrow[u]][col 16 t + kl + 4 q]
     const int o = (A.nout > 1 && sg == 0) ? 1 : 0;
     T* out = reinterpret_cast<T*>(E.blk[A.out_blk[o]]);
 #pragma unroll
     for (int t = 0; t < RT_NCT; ++t) {
       if (t >= nct) continue;
-      const int j = t * 16 + (lane & 15);
-      if (j >= ncol) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = rbase + kl + 4 * q;
-        if (r < nrows) {
-          T* p = out + (size_t)j * E.ld + r;
+        const int j = t * 16 + kl + 4 * q;
+        if (j >= ncol) continue;
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) {
+          if (rrow[u] >= nrows) continue;
+          T* p = out + (size_t)j * E.ld + rrow[u];
           const double prev = A.beta[o] != 0.0 ? A.beta[o] * double(*p) : 0.0;
-          *p = T(prev + A.alpha * acc[t][q]);
+          *p = T(prev + A.alpha * acc[u][t][q]);
         }
       }
     }
@@ -1115,8 +1142,8 @@ int launch_rotate(Ctx& c, int prec, const RotArgs& a_in) {
     }
   }
   TimedScope ts(c, TC_ROT, flops);
-  if (prec == DG_FP64) hipLaunchKernelGGL(k_rotate<double>, g, dim3(256), 0, c.stream, a);
-  else hipLaunchKernelGGL(k_rotate<float>, g, dim3(256), 0, c.stream, a);
+  if (prec == DG_FP64) hipLaunchKernelGGL(k_rotate<double>, g, dim3(RT_THREADS), 0, c.stream, a);
+  else hipLaunchKernelGGL(k_rotate<float>, g, dim3(RT_THREADS), 0, c.stream, a);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
