@@ -28,9 +28,13 @@
  *    valid.  Positive = warning, outputs are valid.  No exception or abort
  *    crosses the interface.  dg_last_error() describes the last failure on
  *    the calling thread.
- *  - A context is bound to one HIP stream and is not thread-safe.  The
- *    library never allocates device memory: the caller provides one arena of
- *    the size dg_query_workspace reports.
+ *  - A context is bound to one HIP stream (the caller's) and is not
+ *    thread-safe.  Internally the elements may be split into groups that run
+ *    on library-owned streams (dg_options.n_streams); their work is ordered
+ *    after the work already queued on the caller's stream and the caller's
+ *    stream waits for it, so the caller sees one stream.  The library never
+ *    allocates device memory: the caller provides one arena of the size
+ *    dg_query_workspace reports.
  */
 #ifndef DG_ALB_H
 #define DG_ALB_H
@@ -86,7 +90,8 @@ typedef struct {
   int32_t n_guard;        /* guard states carried above J_k; < 0: max(4, ceil(J_k/10)) */
   int32_t max_cheb_degree;/* largest Chebyshev degree used by dg_band_energy (0: none)  */
   int32_t ckpt_stride;    /* checkpoint every ckpt_stride filter steps (>= 1)           */
-  int32_t reserved;
+  int32_t n_streams;      /* element groups solved concurrently, each on its own HIP     */
+                          /* stream and host thread (<= 0: 2 for >= 8 elements, else 1) */
 } dg_options;
 
 typedef struct {

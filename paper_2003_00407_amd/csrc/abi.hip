@@ -1,7 +1,21 @@
 // extern "C" entry points declared in include/dg_alb.h: argument checks and
 // dispatch only; no exception crosses this boundary.
+//
+// A context is a batch of element groups.  Each group is an independent
+// solver context (its own arena slice, scratch and HIP stream) over a
+// contiguous range of elements; with several groups, dg_solve_elements drives
+// them from one host thread each, so that one group's latency-bound steps
+// (the per-element Rayleigh-Ritz workgroups, host convergence checks) overlap
+// another group's bandwidth- and MFMA-bound kernels.  Work is forked from and
+// joined back into the caller's stream with events.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <exception>
+#include <memory>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "dg_internal.h"
 
@@ -18,9 +32,149 @@ using dg::Ctx;
     return DG_ERR_ARG;                                  \
   }
 
+namespace {
+
+constexpr int kMaxGroups = 8;
+
+// contiguous element ranges of roughly equal cost (N_k (J_k + g)^2, the subspace GEMMs)
+std::vector<int> split_groups(int n_elem, const dg_element_desc* d, const dg_options* opt) {
+  int ng = opt ? opt->n_streams : 0;
+  if (ng <= 0) {
+    ng = n_elem >= 8 ? 2 : 1;
+    if (const char* s = std::getenv("DG_STREAMS")) ng = std::max(1, std::atoi(s));
+  }
+  ng = std::max(1, std::min({ng, n_elem, kMaxGroups}));
+  std::vector<double> cost(n_elem);
+  double total = 0.0;
+  for (int e = 0; e < n_elem; ++e) {
+    const double N = (double)d[e].n[0] * d[e].n[1] * d[e].n[2];
+    const double k = d[e].n_states + std::max(4.0, std::ceil(0.1 * d[e].n_states));
+    cost[e] = N * k * k;
+    total += cost[e];
+  }
+  std::vector<int> lo(1, 0);
+  double acc = 0.0;
+  for (int e = 0; e < n_elem; ++e) {
+    acc += cost[e];
+    const int g = (int)lo.size();   // groups closed so far + 1
+    const int left_elems = n_elem - 1 - e, left_groups = ng - g;
+    if (g < ng && (acc >= total * g / ng || left_elems == left_groups) && left_elems >= left_groups)
+      lo.push_back(e + 1);
+  }
+  lo.push_back(n_elem);
+  return lo;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
 struct dg_ctx {
-  Ctx impl;
+  std::vector<Ctx> g;            // one solver context per group
+  std::vector<int> lo;           // group element ranges [lo[i], lo[i+1])
+  hipStream_t user = nullptr;    // the caller's stream
+  std::vector<hipStream_t> own;  // library streams (groups > 1)
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
+  std::vector<int64_t> off[6];   // batch-wide packed offsets per dg_offset_kind
+  int be_prec = -1, be_nvec = 0; // last band-energy call (layout of dpsi0)
+  int device = 0;
+
+  int groups() const { return (int)g.size(); }
+  int fork() {
+    if (own.empty()) return DG_OK;
+    DG_HIP(hipEventRecord(fork_ev, user));
+    for (hipStream_t s : own) DG_HIP(hipStreamWaitEvent(s, fork_ev, 0));
+    return DG_OK;
+  }
+  int join() {
+    if (own.empty()) return DG_OK;
+    for (size_t i = 0; i < own.size(); ++i) {
+      DG_HIP(hipEventRecord(join_ev[i], own[i]));
+      DG_HIP(hipStreamWaitEvent(user, join_ev[i], 0));
+    }
+    return DG_OK;
+  }
+  ~dg_ctx() {
+    for (Ctx& c : g) {
+      for (const dg::PendingTime& p : c.pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+      }
+      for (hipEvent_t e : c.event_pool) (void)hipEventDestroy(e);
+    }
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipStream_t s : own) (void)hipStreamDestroy(s);
+  }
 };
+
+namespace {
+
+const std::vector<int64_t>& group_off(const Ctx& c, int kind) {
+  switch (kind) {
+    case DG_OFF_X0: return c.off_x0;
+    case DG_OFF_VEC: return c.off_vec;
+    case DG_OFF_EIG: return c.off_eig;
+    case DG_OFF_ALB: return c.off_alb;
+    case DG_OFF_GRID: return c.off_grid;
+    default: return c.off_kall;
+  }
+}
+
+template <typename P>
+P* shift(P* p, int64_t elems, size_t elem_bytes) {
+  return p ? reinterpret_cast<P*>(reinterpret_cast<char*>(const_cast<void*>((const void*)p)) + elems * elem_bytes)
+           : nullptr;
+}
+
+// run f(group index) for every group, concurrently from one host thread each
+template <typename F>
+int run_groups(dg_ctx* b, F f) {
+  const int ng = b->groups();
+  if (ng == 1) return f(0);
+  std::vector<int> st(ng, DG_OK);
+  std::vector<std::string> err(ng);
+  std::vector<std::thread> th;
+  for (int i = 0; i < ng; ++i)
+    th.emplace_back([&, i]() {
+      (void)hipSetDevice(b->device);
+      try {
+        st[i] = f(i);
+      } catch (const std::exception& ex) {
+        dg::set_error(std::string("internal: ") + ex.what());
+        st[i] = DG_ERR_ARG;
+      } catch (...) {
+        dg::set_error("internal error");
+        st[i] = DG_ERR_ARG;
+      }
+      if (st[i] < 0) err[i] = dg::get_error();
+    });
+  for (auto& t : th) t.join();
+  int worst = DG_OK;
+  for (int i = 0; i < ng; ++i) {
+    if (st[i] < 0) {
+      dg::set_error("element group " + std::to_string(i) + ": " + err[i]);
+      return st[i];
+    }
+    worst = std::max(worst, st[i]);
+  }
+  return worst;
+}
+
+// run f(group index) for every group in turn (asynchronous work on the group streams)
+template <typename F>
+int each_group(dg_ctx* b, F f) {
+  int worst = DG_OK;
+  for (int i = 0; i < b->groups(); ++i) {
+    const int st = f(i);
+    if (st < 0) return st;
+    worst = std::max(worst, st);
+  }
+  return worst;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -42,7 +196,22 @@ const char* dg_last_error(const dg_ctx*) { return dg::get_error(); }
 
 int32_t dg_query_workspace(int32_t n_elem, const dg_element_desc* elems, const dg_options* opt,
                            size_t* bytes) {
-  DG_GUARD(return dg::query_workspace(n_elem, elems, opt, bytes);)
+  DG_GUARD({
+    if (!bytes || !elems || n_elem <= 0) {
+      dg::set_error("bytes or elems is NULL, or n_elem <= 0");
+      return DG_ERR_ARG;
+    }
+    const std::vector<int> lo = split_groups(n_elem, elems, opt);
+    size_t total = 0;
+    for (size_t i = 0; i + 1 < lo.size(); ++i) {
+      size_t b = 0;
+      const int st = dg::query_workspace(lo[i + 1] - lo[i], elems + lo[i], opt, &b);
+      if (st) return st;
+      total += round256(b);
+    }
+    *bytes = total;
+    return DG_OK;
+  })
 }
 
 int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* elems,
@@ -53,14 +222,62 @@ int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* 
       return DG_ERR_ARG;
     }
     *ctx = nullptr;
-    Ctx* c = nullptr;
-    int st = dg::create(&c, n_elem, elems, opt, dev_arena, arena_bytes, hip_stream);
-    if (st < 0) return st;
-    dg_ctx* h = new dg_ctx();
-    h->impl = std::move(*c);
-    delete c;
-    *ctx = h;
-    return st;
+    if (!elems || n_elem <= 0) {
+      dg::set_error("n_elem must be positive and elems non-NULL");
+      return DG_ERR_ARG;
+    }
+    std::unique_ptr<dg_ctx> b(new dg_ctx());
+    b->lo = split_groups(n_elem, elems, opt);
+    b->user = (hipStream_t)hip_stream;
+    DG_HIP(hipGetDevice(&b->device));
+    const int ng = (int)b->lo.size() - 1;
+    if (ng > 1) {
+      DG_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+      for (int i = 0; i < ng; ++i) {
+        hipStream_t s;
+        DG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->own.push_back(s);
+        hipEvent_t ev;
+        DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->join_ev.push_back(ev);
+      }
+      // the arena may still be written by work queued on the caller's stream
+      if (int st = b->fork()) return st;
+    }
+    size_t used = 0;
+    int worst = DG_OK;
+    b->g.reserve(ng);
+    for (int i = 0; i < ng; ++i) {
+      const int n = b->lo[i + 1] - b->lo[i];
+      size_t need = 0;
+      int st = dg::query_workspace(n, elems + b->lo[i], opt, &need);
+      if (st) return st;
+      if (used + need > arena_bytes) {
+        dg::set_error("arena too small for element group " + std::to_string(i));
+        return DG_ERR_OOM;
+      }
+      Ctx* c = nullptr;
+      st = dg::create(&c, n, elems + b->lo[i], opt, (char*)dev_arena + used, arena_bytes - used,
+                      ng > 1 ? (void*)b->own[i] : hip_stream);
+      if (st < 0) return st;
+      worst = std::max(worst, st);
+      b->g.push_back(std::move(*c));
+      delete c;
+      used += round256(need);
+    }
+    // batch-wide offsets: the groups' packed buffers follow each other
+    for (int kind = 0; kind < 6; ++kind) {
+      std::vector<int64_t>& o = b->off[kind];
+      o.assign(1, 0);
+      for (int i = 0; i < ng; ++i) {
+        const std::vector<int64_t>& go = group_off(b->g[i], kind);
+        const int64_t base = o.back();
+        for (size_t e = 1; e < go.size(); ++e) o.push_back(base + go[e]);
+      }
+    }
+    if (int st = b->join()) return st;
+    *ctx = b.release();
+    return worst;
   })
 }
 
@@ -71,18 +288,12 @@ int32_t dg_query_offsets(const dg_ctx* ctx, int32_t kind, int64_t* offsets) {
     dg::set_error("ctx or offsets is NULL");
     return DG_ERR_ARG;
   }
-  const Ctx& c = ctx->impl;
-  const std::vector<int64_t>* v = nullptr;
-  switch (kind) {
-    case DG_OFF_X0: v = &c.off_x0; break;
-    case DG_OFF_VEC: v = &c.off_vec; break;
-    case DG_OFF_EIG: v = &c.off_eig; break;
-    case DG_OFF_ALB: v = &c.off_alb; break;
-    case DG_OFF_GRID: v = &c.off_grid; break;
-    case DG_OFF_KALL: v = &c.off_kall; break;
-    default: dg::set_error("unknown offset kind"); return DG_ERR_ARG;
+  if (kind < 0 || kind > 5) {
+    dg::set_error("unknown offset kind");
+    return DG_ERR_ARG;
   }
-  for (size_t i = 0; i < v->size(); ++i) offsets[i] = (*v)[i];
+  const std::vector<int64_t>& v = ctx->off[kind];
+  for (size_t i = 0; i < v.size(); ++i) offsets[i] = v[i];
   return DG_OK;
 }
 
@@ -92,16 +303,49 @@ int32_t dg_apply_H(dg_ctx* ctx, int32_t elem, int32_t n_vec, int32_t prec, const
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::apply_h(ctx->impl, elem, n_vec, prec, x_dev, y_dev);)
+  DG_GUARD({
+    const int n_elem = ctx->lo.back();
+    if (elem < -1 || elem >= n_elem) {
+      dg::set_error("elem out of range");
+      return DG_ERR_ARG;
+    }
+    const size_t sz = prec == DG_FP32 ? sizeof(float) : sizeof(double);
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int a = ctx->lo[i], z = ctx->lo[i + 1];
+      if (elem >= 0) {
+        if (elem < a || elem >= z) return (int)DG_OK;
+        return dg::apply_h(ctx->g[i], elem - a, n_vec, prec, x_dev, y_dev);
+      }
+      const int64_t o = ctx->off[DG_OFF_GRID][a] * (int64_t)std::max(n_vec, 0);
+      return dg::apply_h(ctx->g[i], -1, n_vec, prec, shift(x_dev, o, sz), shift(y_dev, o, sz));
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_solve_elements(dg_ctx* ctx, const dg_solve_params* params, double* eig_dev,
                           double* resid_dev, int32_t* iters_host) {
-  if (!ctx) {
-    dg::set_error("ctx is NULL");
+  if (!ctx || !params) {
+    dg::set_error("ctx or params is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::solve(ctx->impl, params, eig_dev, resid_dev, iters_host);)
+  DG_GUARD({
+    if (int st = ctx->fork()) return st;
+    int st = run_groups(ctx, [&](int i) {
+      const int a = ctx->lo[i];
+      dg_solve_params p = *params;
+      p.x0_dev = shift(params->x0_dev, ctx->off[DG_OFF_X0][a], sizeof(double));
+      return dg::solve(ctx->g[i], &p, shift(eig_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)),
+                       shift(resid_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)),
+                       iters_host ? iters_host + a : nullptr);
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_get_vectors(dg_ctx* ctx, double* x_dev) {
@@ -109,7 +353,15 @@ int32_t dg_get_vectors(dg_ctx* ctx, double* x_dev) {
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::get_vectors(ctx->impl, x_dev);)
+  DG_GUARD({
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      return dg::get_vectors(ctx->g[i], shift(x_dev, ctx->off[DG_OFF_VEC][ctx->lo[i]], sizeof(double)));
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_make_alb(dg_ctx* ctx, double* alb_dev, double* sval_dev) {
@@ -117,7 +369,17 @@ int32_t dg_make_alb(dg_ctx* ctx, double* alb_dev, double* sval_dev) {
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::make_alb(ctx->impl, alb_dev, sval_dev);)
+  DG_GUARD({
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int a = ctx->lo[i];
+      return dg::make_alb(ctx->g[i], shift(alb_dev, ctx->off[DG_OFF_ALB][a], sizeof(double)),
+                          shift(sval_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)));
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_band_energy(dg_ctx* ctx, int32_t prec, int32_t degree, const double* bounds_host,
@@ -126,7 +388,21 @@ int32_t dg_band_energy(dg_ctx* ctx, int32_t prec, int32_t degree, const double* 
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::band_energy(ctx->impl, prec, degree, bounds_host, n_vec, psi0_dev, f_dev, E_dev);)
+  DG_GUARD({
+    const size_t sz = prec == DG_FP32 ? sizeof(float) : sizeof(double);
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int a = ctx->lo[i];
+      const int64_t o = ctx->off[DG_OFF_GRID][a] * (int64_t)std::max(n_vec, 0);
+      return dg::band_energy(ctx->g[i], prec, degree, bounds_host ? bounds_host + 3 * a : nullptr, n_vec,
+                             shift(psi0_dev, o, sz), f_dev, E_dev ? E_dev + a : nullptr);
+    });
+    if (st < 0) return st;
+    ctx->be_prec = prec;
+    ctx->be_nvec = n_vec;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_band_energy_backward(dg_ctx* ctx, const double* dE_host, void* dpsi0_dev, void* dv_dev) {
@@ -134,7 +410,20 @@ int32_t dg_band_energy_backward(dg_ctx* ctx, const double* dE_host, void* dpsi0_
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::band_energy_backward(ctx->impl, dE_host, dpsi0_dev, dv_dev);)
+  DG_GUARD({
+    const size_t sz = ctx->be_prec == DG_FP32 ? sizeof(float) : sizeof(double);
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int a = ctx->lo[i];
+      const int64_t og = ctx->off[DG_OFF_GRID][a];
+      return dg::band_energy_backward(ctx->g[i], dE_host ? dE_host + a : nullptr,
+                                      shift(dpsi0_dev, og * (int64_t)ctx->be_nvec, sz),
+                                      shift(dv_dev, og, sizeof(double)));
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_set_potential(dg_ctx* ctx, const double* v_dev) {
@@ -142,7 +431,15 @@ int32_t dg_set_potential(dg_ctx* ctx, const double* v_dev) {
     dg::set_error("ctx or v_dev is NULL");
     return DG_ERR_ARG;
   }
-  DG_GUARD(return dg::set_potential(ctx->impl, v_dev);)
+  DG_GUARD({
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      return dg::set_potential(ctx->g[i], shift(v_dev, ctx->off[DG_OFF_GRID][ctx->lo[i]], sizeof(double)));
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
 }
 
 int32_t dg_timing_work(dg_ctx* ctx, double* work_host) {
@@ -150,7 +447,10 @@ int32_t dg_timing_work(dg_ctx* ctx, double* work_host) {
     dg::set_error("ctx or work_host is NULL");
     return DG_ERR_ARG;
   }
-  for (int i = 0; i < dg::TC_N; ++i) work_host[i] = ctx->impl.tacc.work[i];
+  for (int i = 0; i < dg::TC_N; ++i) {
+    work_host[i] = 0.0;
+    for (const Ctx& c : ctx->g) work_host[i] += c.tacc.work[i];
+  }
   return DG_OK;
 }
 
@@ -159,15 +459,24 @@ int32_t dg_timing(dg_ctx* ctx, int32_t enable, int32_t reset, double* ms_host, i
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
   }
-  Ctx& c = ctx->impl;
-  int st = dg::resolve_timing(c);
-  if (st < 0) return st;
-  if (ms_host)
-    for (int i = 0; i < dg::TC_N; ++i) ms_host[i] = c.tacc.ms[i];
-  if (launches_host)
-    for (int i = 0; i < dg::TC_N; ++i) launches_host[i] = c.tacc.launches[i];
-  if (reset) c.tacc = dg::TimingAcc();
-  c.timing = enable != 0;
+  for (Ctx& c : ctx->g) {
+    const int st = dg::resolve_timing(c);
+    if (st < 0) return st;
+  }
+  for (int i = 0; i < dg::TC_N; ++i) {
+    double ms = 0.0;
+    int64_t n = 0;
+    for (const Ctx& c : ctx->g) {
+      ms += c.tacc.ms[i];
+      n += c.tacc.launches[i];
+    }
+    if (ms_host) ms_host[i] = ms;
+    if (launches_host) launches_host[i] = n;
+  }
+  for (Ctx& c : ctx->g) {
+    if (reset) c.tacc = dg::TimingAcc();
+    c.timing = enable != 0;
+  }
   return DG_OK;
 }
 

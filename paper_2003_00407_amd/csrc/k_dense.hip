@@ -679,6 +679,376 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Rayleigh-Ritz for the generalised problem (S = [X W P]) with every working
+// matrix in LDS, for orders up to kRRLdsOrder (one workgroup per element):
+//   scaled overlap -> Cholesky with column dropping -> in-place U^{-1} = Z
+//   -> T = A~ Z, A^ = Z^T T (row-streamed from L2) -> Householder tridiagonal
+//   -> Sturm bisection -> inverse iteration (factors in LDS, batches of
+//   vectors) -> in-order Gram-Schmidt and back-transformation in LDS
+//   -> C = D Z V.
+// The LDS region is reused phase by phase; G keeps Z, Vm the scaled A and then
+// the packed reflectors, Um the eigenvectors of T between phases.
+// ---------------------------------------------------------------------------
+constexpr int kRRLdsBytes = 146000;
+constexpr int kRRLdsOrder = 134;   // np * np doubles fit in kRRLdsBytes
+
+__device__ __forceinline__ int refl_off(int kk, int m) { return kk * (m - 1) - kk * (kk - 1) / 2; }
+
+__global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
+  const int e = blockIdx.x;
+  const ElemDev& E = A.elems[e];
+  if (A.active && !A.active[e]) return;
+  const int K = E.K;
+  const int n = A.nb * K;
+  const int np = n + (n & 1);
+  const int nkeep = kcode(A.nkeep, E);
+  const int KP = E.kmax3 + 2;
+  double* G = E.small + SmallLayout::G(KP);     // in: S^T S (ld n); out: Z (ld np)
+  double* Am = E.small + SmallLayout::A(KP);    // in: S^T H S (ld n); then T; then A^
+  double* Um = E.small + SmallLayout::U(KP);    // staging: Z^T T, then eigenvectors of the tridiagonal
+  double* Vm = E.small + SmallLayout::V(KP);    // scaled A, then packed reflectors
+  double* Cm = E.small + SmallLayout::C(KP);
+  double* vec = E.small + SmallLayout::vec(KP);
+  double* d = vec + VS_D * KP;
+  double* theta = vec + VS_THETA * KP;
+  double* lam_s = vec + VS_FLAGS * KP;
+  extern __shared__ double L[];
+  __shared__ double sh[16];
+  __shared__ int brk;
+  __shared__ double sd[kTriMax], se[kTriMax], stau[kTriMax];
+  __shared__ double vs[kTriMax], ps[kTriMax], ws[kTriMax];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  auto stamp = [&](int k) {
+    if (A.phase_clk && tid == 0) A.phase_clk[e * 8 + k] = wall_clock64();
+  };
+  stamp(0);
+  // ---- scaled overlap in LDS, scaled A in Vm
+  if (tid == 0) brk = 0;
+  __syncthreads();
+  for (int i = tid; i < np; i += nt) {
+    const double gii = i < n ? G[(size_t)i * n + i] : 1.0;
+    if (!(gii > 0.0) && i < K) brk = 1;
+    d[i] = (i < n && gii > 0.0) ? 1.0 / sqrt(gii) : (i < n ? 0.0 : 1.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < np * np; idx += nt) {
+    const int i = idx / np, j = idx % np;
+    const bool in = i < n && j < n;
+    const double s2 = d[i] * d[j];
+    L[idx] = in ? G[(size_t)i * n + j] * s2 : (i == j ? 1.0 : 0.0);
+    Vm[idx] = in ? 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]) * s2 : 0.0;
+  }
+  __syncthreads();
+  // ---- Cholesky L = U^T U (upper, in place); nearly dependent W/P columns leave the basis
+  double pmin = 1.0;
+  int jmin = -1, ndrop = 0;
+  for (int j = 0; j < n; ++j) {
+    const double piv = L[(size_t)j * np + j];
+    if (piv < pmin) {
+      pmin = piv;
+      jmin = j;
+    }
+    if (j >= K && !(piv > A.drop_tol)) {
+      __syncthreads();
+      for (int i = tid; i < n; i += nt) {
+        if (i == j) continue;
+        L[(size_t)i * np + j] = 0.0;
+        L[(size_t)j * np + i] = 0.0;
+        Vm[(size_t)i * np + j] = 0.0;
+        Vm[(size_t)j * np + i] = 0.0;
+      }
+      if (tid == 0) {
+        L[(size_t)j * np + j] = 1.0;
+        Vm[(size_t)j * np + j] = 0.0;
+        d[j] = 0.0;
+      }
+      ++ndrop;
+      __syncthreads();
+      continue;
+    }
+    if (!(piv > A.pivot_tol) && tid == 0) brk = 1;
+    const double ujj = sqrt(fmax(piv, 1e-300));
+    const double inv = 1.0 / ujj;
+    __syncthreads();
+    for (int k = j + 1 + tid; k < n; k += nt) L[(size_t)j * np + k] *= inv;
+    __syncthreads();
+    if (tid == 0) L[(size_t)j * np + j] = ujj;
+    const int mm = n - j - 1;
+    for (int idx = tid; idx < mm * mm; idx += nt) {
+      const int i = j + 1 + idx / mm, k = j + 1 + idx % mm;
+      if (k >= i) L[(size_t)i * np + k] -= L[(size_t)j * np + i] * L[(size_t)j * np + k];
+    }
+    __syncthreads();
+  }
+  if (A.minpiv && tid == 0) {
+    A.minpiv[3 * e] = pmin;
+    A.minpiv[3 * e + 1] = jmin;
+    A.minpiv[3 * e + 2] = ndrop;
+  }
+  if (brk) {
+    // X itself is not positive definite: keep X (C = [I; 0; 0]) and report it
+    for (int idx = tid; idx < n * nkeep; idx += nt) {
+      const int i = idx / nkeep, j = idx % nkeep;
+      Cm[idx] = (i == j) ? 1.0 : 0.0;
+    }
+    if (tid == 0) A.status[e] = 2;
+    return;
+  }
+  if (tid == 0) A.status[e] = 0;
+  stamp(1);
+  // ---- Z = U^{-1} in place, column by column (column j uses the inverted leading block)
+  for (int j = 0; j < n; ++j) {
+    const double ajj = 1.0 / L[(size_t)j * np + j];
+    for (int i = tid; i < j; i += nt) {
+      double t = 0.0;
+      for (int k = i; k < j; ++k) t += L[(size_t)i * np + k] * L[(size_t)k * np + j];
+      ps[i] = t;
+    }
+    __syncthreads();
+    for (int i = tid; i < j; i += nt) L[(size_t)i * np + j] = -ajj * ps[i];
+    if (tid == 0) L[(size_t)j * np + j] = ajj;
+    __syncthreads();
+  }
+  // keep Z for the coefficients
+  for (int idx = tid; idx < np * np; idx += nt) {
+    const int i = idx / np, j = idx % np;
+    G[idx] = (i <= j && j < n) ? L[idx] : 0.0;
+  }
+  stamp(2);
+  // ---- T = A~ Z (Am), then A^ = Z^T T (Um), symmetrised into Am
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx / n, j = idx % n;
+    const double* vr = Vm + (size_t)i * np;
+    double t = 0.0;
+    for (int k = 0; k <= j; ++k) t += vr[k] * L[(size_t)k * np + j];
+    Am[(size_t)i * np + j] = t;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx / n, j = idx % n;
+    double t = 0.0;
+    for (int k = 0; k <= i; ++k) t += L[(size_t)k * np + i] * Am[(size_t)k * np + j];
+    Um[(size_t)i * np + j] = t;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx / n, j = idx % n;
+    L[(size_t)i * np + j] = 0.5 * (Um[(size_t)i * np + j] + Um[(size_t)j * np + i]);
+  }
+  __syncthreads();
+  if (ndrop > 0) {
+    // left-out columns get an eigenvalue above the whole spectrum (Gershgorin bound)
+    double rmax = 0.0;
+    for (int i = tid; i < n; i += nt) {
+      double sacc = 0.0;
+      for (int k = 0; k < n; ++k) sacc += fabs(L[(size_t)i * np + k]);
+      rmax = fmax(rmax, sacc);
+    }
+    rmax = block_max(rmax, sh);
+    for (int j = tid; j < n; j += nt)
+      if (d[j] == 0.0) L[(size_t)j * np + j] = 2.0 * rmax + 1.0;
+    __syncthreads();
+  }
+  stamp(3);
+  // ---- Householder tridiagonalisation in LDS; reflector kk kept in column kk below the diagonal
+  const int m = n;
+  for (int kk = 0; kk < m - 2; ++kk) {
+    const int mr = m - kk - 1;
+    double part = 0.0;
+    for (int i = tid; i < mr; i += nt) {
+      const double x = L[(size_t)(kk + 1 + i) * np + kk];
+      part += x * x;
+    }
+    const double ss = block_sum(part, sh);
+    const double x0 = L[(size_t)(kk + 1) * np + kk];
+    if (tid == 0) sd[kk] = L[(size_t)kk * np + kk];
+    if (ss == 0.0) {
+      if (tid == 0) {
+        stau[kk] = 0.0;
+        se[kk] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
+    const double vv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+    const double tau = 2.0 / vv;
+    for (int i = tid; i < mr; i += nt) vs[i] = (i == 0) ? x0 - alpha : L[(size_t)(kk + 1 + i) * np + kk];
+    if (tid == 0) {
+      stau[kk] = tau;
+      se[kk] = alpha;
+    }
+    __syncthreads();
+    // p = tau A v: one wave per row, lanes along the row
+    for (int i = wv; i < mr; i += nw) {
+      const double* row = L + (size_t)(kk + 1 + i) * np + kk + 1;
+      double acc = 0.0;
+      for (int j = lane; j < mr; j += 64) acc += row[j] * vs[j];
+      acc = wave_sum(acc);
+      if (lane == 0) ps[i] = tau * acc;
+    }
+    __syncthreads();
+    double kp = 0.0;
+    for (int i = tid; i < mr; i += nt) kp += vs[i] * ps[i];
+    const double Kc = 0.5 * tau * block_sum(kp, sh);
+    for (int i = tid; i < mr; i += nt) ws[i] = ps[i] - Kc * vs[i];
+    __syncthreads();
+    for (int idx = tid; idx < mr * mr; idx += nt) {
+      const int i = idx / mr, j = idx % mr;
+      L[(size_t)(kk + 1 + i) * np + kk + 1 + j] -= vs[i] * ws[j] + ws[i] * vs[j];
+    }
+    for (int i = tid; i < mr; i += nt) L[(size_t)(kk + 1 + i) * np + kk] = vs[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (m >= 2) {
+      sd[m - 2] = L[(size_t)(m - 2) * np + m - 2];
+      se[m - 2] = L[(size_t)(m - 1) * np + m - 2];
+      stau[m - 2] = 0.0;
+    }
+    sd[m - 1] = L[(size_t)(m - 1) * np + m - 1];
+    se[m - 1] = 0.0;
+  }
+  // reflectors to Vm, packed by column (rows kk+1 .. m-1 of column kk)
+  for (int kk = wv; kk < m - 2; kk += nw) {
+    double* dst = Vm + refl_off(kk, m);
+    for (int i = lane; i < m - 1 - kk; i += 64) dst[i] = L[(size_t)(kk + 1 + i) * np + kk];
+  }
+  __syncthreads();
+  stamp(6);
+  // ---- eigenvalues by bisection on Sturm counts (thread j -> j-th smallest)
+  __shared__ double sb_lo, sb_hi, sb_norm;
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300, nrm = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m - 1 ? fabs(se[i]) : 0.0);
+      lo = fmin(lo, sd[i] - r);
+      hi = fmax(hi, sd[i] + r);
+      nrm = fmax(nrm, fabs(sd[i]) + r);
+    }
+    sb_norm = fmax(nrm, 1e-300);
+    sb_lo = lo - 1e-12 * sb_norm - 1e-300;
+    sb_hi = hi + 1e-12 * sb_norm + 1e-300;
+  }
+  __syncthreads();
+  const double onenorm = sb_norm;
+  const double pivmin = 1e-300 + 1e-30 * onenorm * onenorm;
+  const int nwant = min(nkeep, m);
+  for (int j = tid; j < nwant; j += nt) lam_s[j] = bisect_eig(sd, se, m, j, sb_lo, sb_hi, pivmin);
+  __syncthreads();
+  // ---- eigenvectors of T by inverse iteration, factors in LDS, R vectors per batch;
+  // eigenvalues closer than ortol ||T|| form a cluster whose vectors are computed in
+  // order, each re-orthogonalised against the earlier ones (read back from Um)
+  __shared__ int cst[kTriMax];
+  __shared__ double shf[kTriMax];
+  __shared__ int maxrank;
+  if (tid == 0) {
+    const double ortol = A.ortol * onenorm, pertol = 10.0 * 2.2e-16 * onenorm;
+    int mr = 0;
+    for (int j = 0; j < nwant; ++j) {
+      cst[j] = (j > 0 && lam_s[j] - lam_s[j - 1] <= ortol) ? cst[j - 1] : j;
+      shf[j] = lam_s[j];
+      if (j > 0 && cst[j] != j && shf[j] < shf[j - 1] + pertol) shf[j] = shf[j - 1] + pertol;
+      mr = max(mr, j - cst[j]);
+    }
+    maxrank = mr;
+  }
+  __syncthreads();
+  double* Zv = Um;   // eigenvector j of T at Zv[j * np + i]
+  const int R = min(nt, kRRLdsBytes / (np * (5 * (int)sizeof(double) + 1)));
+  for (int cb = 0; cb < nwant; cb += R) {
+    for (int rnd = 0; rnd <= maxrank; ++rnd) {
+      const int j = cb + tid;
+      if (tid < R && j < nwant && j - cst[j] == rnd) {
+        StridedD ta{L + 0 * (size_t)np * R + tid, R};
+        StridedD tb{L + 1 * (size_t)np * R + tid, R};
+        StridedD tu{L + 2 * (size_t)np * R + tid, R};
+        StridedD tl{L + 3 * (size_t)np * R + tid, R};
+        StridedD z{L + 4 * (size_t)np * R + tid, R};
+        StridedB pv{reinterpret_cast<unsigned char*>(L + 5 * (size_t)np * R) + tid, R};
+        tri_lu(sd, se, m, shf[j], 2.2e-16 * onenorm, ta, tb, tu, tl, pv);
+        for (int i = 0; i < m; ++i) z[i] = hash_unit(j, i);
+        for (int it = 0; it < 4; ++it) {
+          tri_solve(m, ta, tb, tu, tl, pv, z);
+          for (int q = cst[j]; q < j; ++q) {
+            const double* zq = Zv + (size_t)q * np;
+            double dot = 0.0;
+            for (int i = 0; i < m; ++i) dot += zq[i] * z[i];
+            for (int i = 0; i < m; ++i) z[i] -= dot * zq[i];
+          }
+          double nn = 0.0;
+          for (int i = 0; i < m; ++i) nn += z[i] * z[i];
+          nn = 1.0 / sqrt(nn);
+          for (int i = 0; i < m; ++i) z[i] *= nn;
+        }
+        for (int i = 0; i < np; ++i) Zv[(size_t)j * np + i] = (i < m) ? z[i] : 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  stamp(7);
+  // ---- eigenvectors and reflectors into LDS: in-order Gram-Schmidt, back-transformation
+  double* zl = L;                                  // nwant x np
+  double* rl = L + (size_t)nwant * np;             // packed reflectors
+  const int nrefl = m >= 2 ? refl_off(m - 2, m) : 0;
+  for (int idx = tid; idx < nwant * np; idx += nt) zl[idx] = Zv[idx];
+  for (int idx = tid; idx < nrefl; idx += nt) rl[idx] = Vm[idx];
+  __syncthreads();
+  for (int j = 1; j < nwant; ++j) {
+    double* zj = zl + (size_t)j * np;
+    for (int q = wv; q < j; q += nw) {
+      const double* zq = zl + (size_t)q * np;
+      double dot = 0.0;
+      for (int i = lane; i < m; i += 64) dot += zq[i] * zj[i];
+      dot = wave_sum(dot);
+      if (lane == 0) ps[q] = dot;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int i = tid; i < m; i += nt) {
+      double v = zj[i];
+      for (int q = 0; q < j; ++q) v -= ps[q] * zl[(size_t)q * np + i];
+      zj[i] = v;
+      part += v * v;
+    }
+    const double nn = 1.0 / sqrt(block_sum(part, sh));
+    for (int i = tid; i < m; i += nt) zj[i] *= nn;
+    __syncthreads();
+  }
+  // back-transform: z <- H_0 ... H_{m-3} z (one wave per vector, lanes over rows)
+  for (int j = wv; j < nwant; j += nw) {
+    double* z = zl + (size_t)j * np;
+    for (int kk = m - 3; kk >= 0; --kk) {
+      const double tau = stau[kk];
+      if (tau == 0.0) continue;
+      const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
+      double dot = 0.0;
+      for (int i = lane; i < m - 1 - kk; i += 64) dot += v[i] * z[kk + 1 + i];
+      dot = wave_sum(dot) * tau;
+      for (int i = lane; i < m - 1 - kk; i += 64) z[kk + 1 + i] -= dot * v[i];
+    }
+  }
+  __syncthreads();
+  stamp(4);
+  // ---- C = D Z V[:, :nkeep] (n x nkeep, ld nkeep); left-out rows are zero (d = 0)
+  for (int idx = tid; idx < n * nkeep; idx += nt) {
+    const int i = idx / nkeep, j = idx % nkeep;
+    if (j >= nwant) {
+      Cm[(size_t)i * nkeep + j] = 0.0;
+      continue;
+    }
+    const double* vj = zl + (size_t)j * np;
+    double sacc = 0.0;
+    for (int k = i; k < n; ++k) sacc += G[(size_t)i * np + k] * vj[k];
+    Cm[(size_t)i * nkeep + j] = d[i] * sacc;
+  }
+  for (int j = tid; j < nkeep; j += nt) theta[j] = j < nwant ? lam_s[j] : 0.0;
+  __syncthreads();
+  stamp(5);
+}
+
+// ---------------------------------------------------------------------------
 // rotation: out_o[:, j] = beta_o out_o[:, j] + alpha sum_{c in [c0_o, c1_o)} S[:, c] C[c, j]
 // ---------------------------------------------------------------------------
 constexpr int RT_THREADS = 512;
@@ -1114,11 +1484,26 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
     const double k = nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]);
     flops += (mode == RR_GEN ? 2.0 / 3.0 + 2.0 : 0.0) * n * n * n + 4.0 / 3.0 * n * n * n + 4.0 * n * n * k;
   }
+  // RR_GEN with every working matrix in LDS when the orders allow it
+  bool lds_gen = mode == RR_GEN && npmax <= kRRLdsOrder;
+  if (lds_gen) {
+    for (int e = 0; e < c.n_elem; ++e) {
+      const int n = nb * c.K[e], npe = n + (n & 1);
+      const int nw = std::min(nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]), n);
+      if ((size_t)(nw * npe + n * (n - 1) / 2) * sizeof(double) > (size_t)kRRLdsBytes) lds_gen = false;
+    }
+  }
   RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status, use_lds ? npmax : 0,
            c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
            c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol};
   TimedScope ts(c, TC_RR, flops);
-  hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
+  if (lds_gen) {
+    static const bool attr = set_lds_limit((const void*)k_rr_lds, kRRLdsBytes);
+    (void)attr;
+    hipLaunchKernelGGL(k_rr_lds, dim3(c.n_elem), dim3(kRRThreads), kRRLdsBytes, c.stream, a);
+  } else {
+    hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
+  }
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

@@ -44,7 +44,7 @@ class ElementDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("n_guard", C.c_int32), ("max_cheb_degree", C.c_int32), ("ckpt_stride", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("n_streams", C.c_int32)]
 
 
 class SolveParams(C.Structure):
