@@ -740,11 +740,13 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     Vm[idx] = in ? 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]) * s2 : 0.0;
   }
   __syncthreads();
-  // ---- Cholesky L = U^T U (upper, in place); nearly dependent W/P columns leave the basis
+  // ---- Cholesky L = U^T U (upper, in place); nearly dependent W/P columns leave the basis.
+  // Rows keep their unscaled values during the elimination (one barrier per
+  // column); the rows are divided by sqrt(pivot) at the end.
   double pmin = 1.0;
   int jmin = -1, ndrop = 0;
   for (int j = 0; j < n; ++j) {
-    const double piv = L[(size_t)j * np + j];
+    const double piv = L[j * np + j];
     if (piv < pmin) {
       pmin = piv;
       jmin = j;
@@ -753,34 +755,40 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       __syncthreads();
       for (int i = tid; i < n; i += nt) {
         if (i == j) continue;
-        L[(size_t)i * np + j] = 0.0;
-        L[(size_t)j * np + i] = 0.0;
+        L[i * np + j] = 0.0;
+        L[j * np + i] = 0.0;
         Vm[(size_t)i * np + j] = 0.0;
         Vm[(size_t)j * np + i] = 0.0;
       }
       if (tid == 0) {
-        L[(size_t)j * np + j] = 1.0;
+        L[j * np + j] = 1.0;
         Vm[(size_t)j * np + j] = 0.0;
         d[j] = 0.0;
+        ws[j] = 1.0;
       }
       ++ndrop;
       __syncthreads();
       continue;
     }
     if (!(piv > A.pivot_tol) && tid == 0) brk = 1;
-    const double ujj = sqrt(fmax(piv, 1e-300));
-    const double inv = 1.0 / ujj;
-    __syncthreads();
-    for (int k = j + 1 + tid; k < n; k += nt) L[(size_t)j * np + k] *= inv;
-    __syncthreads();
-    if (tid == 0) L[(size_t)j * np + j] = ujj;
-    const int mm = n - j - 1;
-    for (int idx = tid; idx < mm * mm; idx += nt) {
-      const int i = j + 1 + idx / mm, k = j + 1 + idx % mm;
-      if (k >= i) L[(size_t)i * np + k] -= L[(size_t)j * np + i] * L[(size_t)j * np + k];
+    const double pinv = 1.0 / fmax(piv, 1e-300);
+    if (tid == 0) ws[j] = sqrt(fmax(piv, 1e-300));
+    for (int i = j + 1 + wv; i < n; i += nw) {
+      const double f = L[j * np + i] * pinv;
+      double* row = L + i * np;
+      const double* rj = L + j * np;
+      for (int k = i + lane; k < n; k += 64) row[k] -= f * rj[k];
     }
     __syncthreads();
   }
+  // divide row j by sqrt(pivot_j): U
+  for (int j = wv; j < n; j += nw) {
+    const double u = ws[j];
+    double* row = L + j * np;
+    for (int k = j + 1 + lane; k < n; k += 64) row[k] = (d[j] == 0.0 && k != j) ? 0.0 : row[k] / u;
+    if (lane == 0) row[j] = u;
+  }
+  __syncthreads();
   if (A.minpiv && tid == 0) {
     A.minpiv[3 * e] = pmin;
     A.minpiv[3 * e + 1] = jmin;
@@ -797,39 +805,69 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   }
   if (tid == 0) A.status[e] = 0;
   stamp(1);
-  // ---- Z = U^{-1} in place, column by column (column j uses the inverted leading block)
+  // ---- Z = U^{-1} in place, column by column (column j uses the inverted leading block):
+  // Z[i][j] = -(1/U[j][j]) sum_{k=i}^{j-1} Z[i][k] U[k][j]
   for (int j = 0; j < n; ++j) {
-    const double ajj = 1.0 / L[(size_t)j * np + j];
-    for (int i = tid; i < j; i += nt) {
+    for (int k = tid; k < j; k += nt) vs[k] = L[k * np + j];
+    __syncthreads();
+    const double ajj = 1.0 / L[j * np + j];
+    for (int i = wv; i < j; i += nw) {
+      const double* zi = L + i * np;
       double t = 0.0;
-      for (int k = i; k < j; ++k) t += L[(size_t)i * np + k] * L[(size_t)k * np + j];
-      ps[i] = t;
+      for (int k = i + lane; k < j; k += 64) t += zi[k] * vs[k];
+      t = wave_sum(t);
+      if (lane == 0) ps[i] = -ajj * t;
     }
     __syncthreads();
-    for (int i = tid; i < j; i += nt) L[(size_t)i * np + j] = -ajj * ps[i];
-    if (tid == 0) L[(size_t)j * np + j] = ajj;
-    __syncthreads();
+    for (int i = tid; i < j; i += nt) L[i * np + j] = ps[i];
+    if (tid == 0) L[j * np + j] = ajj;
   }
+  __syncthreads();
   // keep Z for the coefficients
   for (int idx = tid; idx < np * np; idx += nt) {
     const int i = idx / np, j = idx % np;
     G[idx] = (i <= j && j < n) ? L[idx] : 0.0;
   }
   stamp(2);
-  // ---- T = A~ Z (Am), then A^ = Z^T T (Um), symmetrised into Am
-  for (int idx = tid; idx < n * n; idx += nt) {
-    const int i = idx / n, j = idx % n;
-    const double* vr = Vm + (size_t)i * np;
-    double t = 0.0;
-    for (int k = 0; k <= j; ++k) t += vr[k] * L[(size_t)k * np + j];
-    Am[(size_t)i * np + j] = t;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += nt) {
-    const int i = idx / n, j = idx % n;
-    double t = 0.0;
-    for (int k = 0; k <= i; ++k) t += L[(size_t)k * np + i] * Am[(size_t)k * np + j];
-    Um[(size_t)i * np + j] = t;
+  // ---- T = A~ Z (Am), then A^ = Z^T T (Um), as 16x16 FP64 MFMA tiles (one wave per tile)
+  {
+    const int nt16 = (n + 15) >> 4;
+    const int kst = (n + 3) >> 2;
+    for (int t = wv; t < nt16 * nt16; t += nw) {
+      const int ti = t / nt16, tj = t % nt16;
+      const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
+      const int kmax = min(kst, (tj * 16 + 16 + 3) >> 2);   // Z[k][j] = 0 for k > j
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      for (int ks = 0; ks < kmax; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const double av = (ia < n && k < n) ? Vm[(size_t)ia * np + k] : 0.0;
+        const double bv = (jb < n && k <= jb) ? L[k * np + jb] : 0.0;
+        acc = mfma16x16x4(av, bv, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ti * 16 + (lane >> 4) + 4 * q;
+        if (i < n && jb < n) Am[(size_t)i * np + jb] = acc[q];
+      }
+    }
+    __syncthreads();
+    for (int t = wv; t < nt16 * nt16; t += nw) {
+      const int ti = t / nt16, tj = t % nt16;
+      const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
+      const int kmax = min(kst, (ti * 16 + 16 + 3) >> 2);   // Z[k][i] = 0 for k > i
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      for (int ks = 0; ks < kmax; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const double av = (ia < n && k <= ia) ? L[k * np + ia] : 0.0;
+        const double bv = (jb < n && k < n) ? Am[(size_t)k * np + jb] : 0.0;
+        acc = mfma16x16x4(av, bv, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ti * 16 + (lane >> 4) + 4 * q;
+        if (i < n && jb < n) Um[(size_t)i * np + jb] = acc[q];
+      }
+    }
   }
   __syncthreads();
   for (int idx = tid; idx < n * n; idx += nt) {
@@ -853,52 +891,54 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   stamp(3);
   // ---- Householder tridiagonalisation in LDS; reflector kk kept in column kk below the diagonal
   const int m = n;
+  __shared__ int skip;
   for (int kk = 0; kk < m - 2; ++kk) {
     const int mr = m - kk - 1;
-    double part = 0.0;
-    for (int i = tid; i < mr; i += nt) {
-      const double x = L[(size_t)(kk + 1 + i) * np + kk];
-      part += x * x;
-    }
-    const double ss = block_sum(part, sh);
-    const double x0 = L[(size_t)(kk + 1) * np + kk];
-    if (tid == 0) sd[kk] = L[(size_t)kk * np + kk];
-    if (ss == 0.0) {
-      if (tid == 0) {
-        stau[kk] = 0.0;
-        se[kk] = 0.0;
+    if (wv == 0) {
+      // reflector from column kk (one wave)
+      double part = 0.0;
+      for (int i = lane; i < mr; i += 64) {
+        const double x = L[(kk + 1 + i) * np + kk];
+        part += x * x;
       }
-      __syncthreads();
-      continue;
-    }
-    const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
-    const double vv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-    const double tau = 2.0 / vv;
-    for (int i = tid; i < mr; i += nt) vs[i] = (i == 0) ? x0 - alpha : L[(size_t)(kk + 1 + i) * np + kk];
-    if (tid == 0) {
-      stau[kk] = tau;
-      se[kk] = alpha;
+      const double ss = wave_sum(part);
+      const double x0 = L[(kk + 1) * np + kk];
+      const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
+      const double vv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+      const bool zero = !(ss > 0.0);
+      for (int i = lane; i < mr; i += 64) vs[i] = (i == 0) ? x0 - alpha : L[(kk + 1 + i) * np + kk];
+      if (lane == 0) {
+        sd[kk] = L[kk * np + kk];
+        stau[kk] = zero ? 0.0 : 2.0 / vv;
+        se[kk] = zero ? 0.0 : alpha;
+        skip = zero ? 1 : 0;
+      }
     }
     __syncthreads();
+    if (skip) continue;
+    const double tau = stau[kk];
     // p = tau A v: one wave per row, lanes along the row
     for (int i = wv; i < mr; i += nw) {
-      const double* row = L + (size_t)(kk + 1 + i) * np + kk + 1;
+      const double* row = L + (kk + 1 + i) * np + kk + 1;
       double acc = 0.0;
       for (int j = lane; j < mr; j += 64) acc += row[j] * vs[j];
       acc = wave_sum(acc);
       if (lane == 0) ps[i] = tau * acc;
     }
     __syncthreads();
-    double kp = 0.0;
-    for (int i = tid; i < mr; i += nt) kp += vs[i] * ps[i];
-    const double Kc = 0.5 * tau * block_sum(kp, sh);
-    for (int i = tid; i < mr; i += nt) ws[i] = ps[i] - Kc * vs[i];
-    __syncthreads();
-    for (int idx = tid; idx < mr * mr; idx += nt) {
-      const int i = idx / mr, j = idx % mr;
-      L[(size_t)(kk + 1 + i) * np + kk + 1 + j] -= vs[i] * ws[j] + ws[i] * vs[j];
+    if (wv == 0) {
+      double kp = 0.0;
+      for (int i = lane; i < mr; i += 64) kp += vs[i] * ps[i];
+      const double Kc = 0.5 * tau * wave_sum(kp);
+      for (int i = lane; i < mr; i += 64) ws[i] = ps[i] - Kc * vs[i];
     }
-    for (int i = tid; i < mr; i += nt) L[(size_t)(kk + 1 + i) * np + kk] = vs[i];
+    __syncthreads();
+    for (int i = wv; i < mr; i += nw) {
+      double* row = L + (kk + 1 + i) * np + kk + 1;
+      const double vi = vs[i], wi = ws[i];
+      for (int j = lane; j < mr; j += 64) row[j] -= vi * ws[j] + wi * vs[j];
+      if (lane == 0) L[(kk + 1 + i) * np + kk] = vi;
+    }
     __syncthreads();
   }
   if (tid == 0) {
@@ -957,16 +997,18 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   __syncthreads();
   double* Zv = Um;   // eigenvector j of T at Zv[j * np + i]
   const int R = min(nt, kRRLdsBytes / (np * (5 * (int)sizeof(double) + 1)));
+  // vector slot of this thread: slots spread over the waves (latency hiding)
+  const int slot = (lane < (R + nw - 1) / nw) ? lane * nw + wv : R;
   for (int cb = 0; cb < nwant; cb += R) {
     for (int rnd = 0; rnd <= maxrank; ++rnd) {
-      const int j = cb + tid;
-      if (tid < R && j < nwant && j - cst[j] == rnd) {
-        StridedD ta{L + 0 * (size_t)np * R + tid, R};
-        StridedD tb{L + 1 * (size_t)np * R + tid, R};
-        StridedD tu{L + 2 * (size_t)np * R + tid, R};
-        StridedD tl{L + 3 * (size_t)np * R + tid, R};
-        StridedD z{L + 4 * (size_t)np * R + tid, R};
-        StridedB pv{reinterpret_cast<unsigned char*>(L + 5 * (size_t)np * R) + tid, R};
+      const int j = cb + slot;
+      if (slot < R && j < nwant && j - cst[j] == rnd) {
+        StridedD ta{L + 0 * (size_t)np * R + slot, R};
+        StridedD tb{L + 1 * (size_t)np * R + slot, R};
+        StridedD tu{L + 2 * (size_t)np * R + slot, R};
+        StridedD tl{L + 3 * (size_t)np * R + slot, R};
+        StridedD z{L + 4 * (size_t)np * R + slot, R};
+        StridedB pv{reinterpret_cast<unsigned char*>(L + 5 * (size_t)np * R) + slot, R};
         tri_lu(sd, se, m, shf[j], 2.2e-16 * onenorm, ta, tb, tu, tl, pv);
         for (int i = 0; i < m; ++i) z[i] = hash_unit(j, i);
         for (int it = 0; it < 4; ++it) {
@@ -996,24 +1038,26 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   for (int idx = tid; idx < nrefl; idx += nt) rl[idx] = Vm[idx];
   __syncthreads();
   for (int j = 1; j < nwant; ++j) {
-    double* zj = zl + (size_t)j * np;
+    double* zj = zl + j * np;
     for (int q = wv; q < j; q += nw) {
-      const double* zq = zl + (size_t)q * np;
+      const double* zq = zl + q * np;
       double dot = 0.0;
       for (int i = lane; i < m; i += 64) dot += zq[i] * zj[i];
       dot = wave_sum(dot);
       if (lane == 0) ps[q] = dot;
     }
     __syncthreads();
-    double part = 0.0;
-    for (int i = tid; i < m; i += nt) {
-      double v = zj[i];
-      for (int q = 0; q < j; ++q) v -= ps[q] * zl[(size_t)q * np + i];
-      zj[i] = v;
-      part += v * v;
+    if (wv == 0) {
+      double part = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        double v = zj[i];
+        for (int q = 0; q < j; ++q) v -= ps[q] * zl[q * np + i];
+        zj[i] = v;
+        part += v * v;
+      }
+      const double nn = 1.0 / sqrt(wave_sum(part));
+      for (int i = lane; i < m; i += 64) zj[i] *= nn;
     }
-    const double nn = 1.0 / sqrt(block_sum(part, sh));
-    for (int i = tid; i < m; i += nt) zj[i] *= nn;
     __syncthreads();
   }
   // back-transform: z <- H_0 ... H_{m-3} z (one wave per vector, lanes over rows)
@@ -1063,8 +1107,8 @@ constexpr int RT_NCT = RT_MAXC / 16;
 // results are 16 consecutive grid rows of one column (128-byte stores).
 // With two outputs whose C row ranges nest (range 1 is a suffix of range 0),
 // the suffix is accumulated first, stored as output 1, then completed.
-template <typename T>
-__global__ void __launch_bounds__(RT_THREADS) k_rotate(RotArgs A) {
+template <typename T, int NCT>
+__global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs A) {
   const int e = blockIdx.y;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
@@ -1087,11 +1131,11 @@ __global__ void __launch_bounds__(RT_THREADS) k_rotate(RotArgs A) {
   for (int u = 0; u < RT_RT; ++u) rrow[u] = r0 + (w * RT_RT + u) * 16 + (lane & 15);
   const int nct = (ncol + 15) / 16;
   const double* Cm = E.small + soff(A.c_off, E);
-  d4v acc[RT_RT][RT_NCT];
+  d4v acc[RT_RT][NCT];
 #pragma unroll
   for (int u = 0; u < RT_RT; ++u)
 #pragma unroll
-    for (int t = 0; t < RT_NCT; ++t) acc[u][t] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NCT; ++t) acc[u][t] = d4v{0.0, 0.0, 0.0, 0.0};
   const int nseg = A.nout > 1 ? 2 : 1;
   for (int sg = 0; sg < nseg; ++sg) {
     // segment bounds
@@ -1117,8 +1161,8 @@ __global__ void __launch_bounds__(RT_THREADS) k_rotate(RotArgs A) {
     if (lo < hi) load_s(lo, an);
     for (int cb = lo; cb < hi; cb += RT_CC) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < RT_CC * RT_MAXC; idx += RT_THREADS) {
-        const int cc = idx / RT_MAXC, j = idx % RT_MAXC;
+      for (int idx = threadIdx.x; idx < RT_CC * NCT * 16; idx += RT_THREADS) {
+        const int cc = idx / (NCT * 16), j = idx % (NCT * 16);
         const int c = cb + cc;
         sc[cc][j] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
       }
@@ -1131,7 +1175,7 @@ __global__ void __launch_bounds__(RT_THREADS) k_rotate(RotArgs A) {
 #pragma unroll
       for (int ks = 0; ks < RT_CC / 4; ++ks) {
 #pragma unroll
-        for (int t = 0; t < RT_NCT; ++t) {
+        for (int t = 0; t < NCT; ++t) {
           if (t >= nct) continue;
           const double cv = sc[ks * 4 + kl][t * 16 + (lane & 15)];
 #pragma unroll
@@ -1143,7 +1187,7 @@ __global__ void __launch_bounds__(RT_THREADS) k_rotate(RotArgs A) {
     const int o = (A.nout > 1 && sg == 0) ? 1 : 0;
     T* out = reinterpret_cast<T*>(E.blk[A.out_blk[o]]);
 #pragma unroll
-    for (int t = 0; t < RT_NCT; ++t) {
+    for (int t = 0; t < NCT; ++t) {
       if (t >= nct) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1527,8 +1571,14 @@ int launch_rotate(Ctx& c, int prec, const RotArgs& a_in) {
     }
   }
   TimedScope ts(c, TC_ROT, flops);
-  if (prec == DG_FP64) hipLaunchKernelGGL(k_rotate<double>, g, dim3(RT_THREADS), 0, c.stream, a);
-  else hipLaunchKernelGGL(k_rotate<float>, g, dim3(RT_THREADS), 0, c.stream, a);
+  // output column tiles: 3 (up to 48 columns) or 6 (up to 96)
+  if (k <= 48) {
+    if (prec == DG_FP64) hipLaunchKernelGGL((k_rotate<double, 3>), g, dim3(RT_THREADS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rotate<float, 3>), g, dim3(RT_THREADS), 0, c.stream, a);
+  } else {
+    if (prec == DG_FP64) hipLaunchKernelGGL((k_rotate<double, 6>), g, dim3(RT_THREADS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rotate<float, 6>), g, dim3(RT_THREADS), 0, c.stream, a);
+  }
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
