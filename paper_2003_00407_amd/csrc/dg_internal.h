@@ -188,7 +188,7 @@ struct ColSet {
   int nb;
   int blk[3];
 };
-enum RRMode { RR_GEN = 0, RR_SVD = 1 };
+enum RRMode { RR_GEN = 0, RR_SVD = 1, RR_CHOLQR = 2 };
 struct RotArgs {
   const ElemDev* elems;
   const int* active;

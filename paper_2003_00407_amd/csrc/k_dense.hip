@@ -699,7 +699,9 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
   const int K = E.K;
-  const int n = A.nb * K;
+  const bool gen = A.mode == RR_GEN, svd = A.mode == RR_SVD;
+  const int n = gen ? A.nb * K : kcode(A.kfix, E);
+  const int kx = gen ? K : n;             // leading columns that are never left out
   const int np = n + (n & 1);
   const int nkeep = kcode(A.nkeep, E);
   const int KP = E.kmax3 + 2;
@@ -723,12 +725,21 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     if (A.phase_clk && tid == 0) A.phase_clk[e * 8 + k] = wall_clock64();
   };
   stamp(0);
-  // ---- scaled overlap in LDS, scaled A in Vm
   if (tid == 0) brk = 0;
   __syncthreads();
+  int ndrop = 0;
+  if (svd) {
+    // eigen-decomposition of the Gram matrix itself
+    for (int idx = tid; idx < np * np; idx += nt) {
+      const int i = idx / np, j = idx % np;
+      L[idx] = (i < n && j < n) ? G[(size_t)i * n + j] : 0.0;
+    }
+    __syncthreads();
+  } else {
+  // ---- scaled overlap in LDS, scaled A in Vm
   for (int i = tid; i < np; i += nt) {
     const double gii = i < n ? G[(size_t)i * n + i] : 1.0;
-    if (!(gii > 0.0) && i < K) brk = 1;
+    if (!(gii > 0.0) && i < kx) brk = 1;
     d[i] = (i < n && gii > 0.0) ? 1.0 / sqrt(gii) : (i < n ? 0.0 : 1.0);
   }
   __syncthreads();
@@ -737,21 +748,21 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     const bool in = i < n && j < n;
     const double s2 = d[i] * d[j];
     L[idx] = in ? G[(size_t)i * n + j] * s2 : (i == j ? 1.0 : 0.0);
-    Vm[idx] = in ? 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]) * s2 : 0.0;
+    if (gen) Vm[idx] = in ? 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]) * s2 : 0.0;
   }
   __syncthreads();
   // ---- Cholesky L = U^T U (upper, in place); nearly dependent W/P columns leave the basis.
   // Rows keep their unscaled values during the elimination (one barrier per
   // column); the rows are divided by sqrt(pivot) at the end.
   double pmin = 1.0;
-  int jmin = -1, ndrop = 0;
+  int jmin = -1;
   for (int j = 0; j < n; ++j) {
     const double piv = L[j * np + j];
     if (piv < pmin) {
       pmin = piv;
       jmin = j;
     }
-    if (j >= K && !(piv > A.drop_tol)) {
+    if (j >= kx && !(piv > A.drop_tol)) {
       __syncthreads();
       for (int i = tid; i < n; i += nt) {
         if (i == j) continue;
@@ -823,6 +834,15 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     if (tid == 0) L[j * np + j] = ajj;
   }
   __syncthreads();
+  if (!gen) {
+    // Cholesky QR: C = D Z orthonormalises the columns (n x nkeep)
+    for (int idx = tid; idx < n * nkeep; idx += nt) {
+      const int i = idx / nkeep, j = idx % nkeep;
+      Cm[idx] = (i <= j && j < n) ? d[i] * L[i * np + j] : 0.0;
+    }
+    stamp(5);
+    return;
+  }
   // keep Z for the coefficients
   for (int idx = tid; idx < np * np; idx += nt) {
     const int i = idx / np, j = idx % np;
@@ -888,6 +908,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       if (d[j] == 0.0) L[(size_t)j * np + j] = 2.0 * rmax + 1.0;
     __syncthreads();
   }
+  }   // !svd
   stamp(3);
   // ---- Householder tridiagonalisation in LDS; reflector kk kept in column kk below the diagonal
   const int m = n;
@@ -974,7 +995,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   __syncthreads();
   const double onenorm = sb_norm;
   const double pivmin = 1e-300 + 1e-30 * onenorm * onenorm;
-  const int nwant = min(nkeep, m);
+  const int nwant = svd ? m : min(nkeep, m);
   for (int j = tid; j < nwant; j += nt) lam_s[j] = bisect_eig(sd, se, m, j, sb_lo, sb_hi, pivmin);
   __syncthreads();
   // ---- eigenvectors of T by inverse iteration, factors in LDS, R vectors per batch;
@@ -1075,6 +1096,19 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   }
   __syncthreads();
   stamp(4);
+  if (svd) {
+    // C = V[:, sel] / sigma with sigma = sqrt(eigenvalue), descending
+    for (int idx = tid; idx < n * nkeep; idx += nt) {
+      const int i = idx / nkeep, j = idx % nkeep;
+      const int col = m - 1 - j;
+      const double sg = (col >= 0) ? sqrt(fmax(lam_s[col], 0.0)) : 0.0;
+      Cm[idx] = (col >= 0 && sg > 0.0) ? zl[col * np + i] / sg : 0.0;
+    }
+    for (int j = tid; j < nkeep; j += nt) theta[j] = (m - 1 - j >= 0) ? sqrt(fmax(lam_s[m - 1 - j], 0.0)) : 0.0;
+    __syncthreads();
+    stamp(5);
+    return;
+  }
   // ---- C = D Z V[:, :nkeep] (n x nkeep, ld nkeep); left-out rows are zero (d = 0)
   for (int idx = tid; idx < n * nkeep; idx += nt) {
     const int i = idx / nkeep, j = idx % nkeep;
@@ -1528,12 +1562,13 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
     const double k = nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]);
     flops += (mode == RR_GEN ? 2.0 / 3.0 + 2.0 : 0.0) * n * n * n + 4.0 / 3.0 * n * n * n + 4.0 * n * n * k;
   }
-  // RR_GEN with every working matrix in LDS when the orders allow it
-  bool lds_gen = mode == RR_GEN && npmax <= kRRLdsOrder;
+  // every working matrix in LDS when the orders allow it (always for Cholesky QR)
+  bool lds_gen = npmax <= kRRLdsOrder;
   if (lds_gen) {
     for (int e = 0; e < c.n_elem; ++e) {
-      const int n = nb * c.K[e], npe = n + (n & 1);
-      const int nw = std::min(nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]), n);
+      const int n = mode == RR_GEN ? nb * c.K[e] : (kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
+      const int npe = n + (n & 1);
+      const int nw = mode == RR_SVD ? n : std::min(nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]), n);
       if ((size_t)(nw * npe + n * (n - 1) / 2) * sizeof(double) > (size_t)kRRLdsBytes) lds_gen = false;
     }
   }
@@ -1541,6 +1576,10 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
            c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
            c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol};
   TimedScope ts(c, TC_RR, flops);
+  if (!lds_gen && mode == RR_CHOLQR) {
+    set_error("Cholesky QR of an order above the LDS limit");
+    return DG_ERR_SHAPE;
+  }
   if (lds_gen) {
     static const bool attr = set_lds_limit((const void*)k_rr_lds, kRRLdsBytes);
     (void)attr;

@@ -333,9 +333,9 @@ int make_alb(Ctx& c, double* alb, double* sval) {
   ra.c_blockrows = 1;
   ra.rows_e = 1;
   if ((st = launch_rotate(c, DG_FP64, ra))) return st;
-  // second pass restores orthonormality to working precision
+  // second pass (Cholesky QR) restores orthonormality to working precision
   if ((st = launch_gram_rows(c, DG_FP64, S1, KC_J, S1, KC_J, small_code(0), 1, 1))) return st;
-  if ((st = launch_rr(c, 0, KC_J, KC_J, RR_SVD, nullptr))) return st;
+  if ((st = launch_rr(c, 0, KC_J, KC_J, RR_CHOLQR, nullptr))) return st;
   ra.S = S1;
   ra.out_blk[0] = t0;
   if ((st = launch_rotate(c, DG_FP64, ra))) return st;

@@ -131,10 +131,10 @@ class HostDescs:
 
 
 def query_workspace(elements: Sequence, n_guard: int = -1, max_cheb_degree: int = 0,
-                    ckpt_stride: int = 1) -> int:
+                    ckpt_stride: int = 1, n_streams: int = 0) -> int:
     """Arena bytes for these elements (CPU only, never touches the GPU)."""
     hd = HostDescs(elements)
-    opt = Options(n_guard, max_cheb_degree, ckpt_stride, 0)
+    opt = Options(n_guard, max_cheb_degree, ckpt_stride, n_streams)
     out = C.c_size_t(0)
     _check(_lib.dg_query_workspace(hd.n, hd.arr, C.byref(opt), C.byref(out)), "dg_query_workspace")
     return int(out.value)
@@ -144,13 +144,13 @@ class Elements:
     """A batch of extended elements resident on one GPU (the dg_ctx)."""
 
     def __init__(self, elements: Sequence, n_guard: int = -1, max_cheb_degree: int = 0,
-                 ckpt_stride: int = 1, device: str = "cuda:0"):
+                 ckpt_stride: int = 1, n_streams: int = 0, device: str = "cuda:0"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.elements = list(elements)
         self.hd = HostDescs(self.elements)
-        self.opt = Options(n_guard, max_cheb_degree, ckpt_stride, 0)
+        self.opt = Options(n_guard, max_cheb_degree, ckpt_stride, n_streams)
         nbytes = C.c_size_t(0)
         _check(_lib.dg_query_workspace(self.hd.n, self.hd.arr, C.byref(self.opt), C.byref(nbytes)),
                "dg_query_workspace")
