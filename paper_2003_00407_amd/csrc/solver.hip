@@ -100,7 +100,7 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   return launch_permute(c, perm, active);
 }
 
-static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done) {
+static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done, bool carry_p = false) {
   int st;
   int* active = c.dev_active;
   // an FP32 stage stops an element once its residual stops improving (FP32 floor)
@@ -120,8 +120,13 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
   c.rr_pivot_tol = (prec == DG_FP64) ? 1e-13 : 1e-6;
   c.rr_drop_tol = c.rr_drop_env >= 0.0 ? c.rr_drop_env : (prec == DG_FP64 ? 1e-8 : 1e-4);
   if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
+  // (the start rotation leaves the block in T1 as P: a carried search direction)
   if ((st = rr_and_rotate(c, prec, 1, active, false))) return st;
   bool have_p = false;
+  if (carry_p) {
+    if ((st = launch_hpsi(c, -1, 0, prec, B_P, B_HP, active))) return st;
+    have_p = true;
+  }
   std::vector<int> it_elem(c.n_elem, 0);
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
@@ -273,13 +278,16 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
                                 : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree,
                                             it1.data(), &done);
     if (st < 0) return st;
-    // promote X to FP64 (into W's storage), then FP64 refinement sweeps
+    // promote X (into W's storage) and, for LOBPCG, the last search direction P (into
+    // T1, which the start rotation turns into P) to FP64, then FP64 refinement sweeps
     if ((st = launch_convert(c, B_X, DG_FP32, B_W, DG_FP64, KC_K))) return st;
+    const bool carry = p->method == DG_LOBPCG;
+    if (carry && (st = launch_convert(c, B_P, DG_FP32, B_T1, DG_FP64, KC_K))) return st;
     {
       int perm[kMaxBlocks] = {B_W, B_X, B_P, B_HX, B_HW, B_HP, B_T0, B_T1};
       if ((st = launch_permute(c, perm, nullptr))) return st;
     }
-    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done);
+    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry);
     if (st < 0) return st;
   }
   c.solved = true;
