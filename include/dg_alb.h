@@ -91,7 +91,8 @@ typedef struct {
   int32_t max_cheb_degree;/* largest Chebyshev degree used by dg_band_energy (0: none)  */
   int32_t ckpt_stride;    /* checkpoint every ckpt_stride filter steps (>= 1)           */
   int32_t n_streams;      /* element groups solved concurrently, each on its own HIP     */
-                          /* stream and host thread (<= 0: 1, or the DG_STREAMS value)  */
+                          /* stream and host thread (<= 0: n_elem / 4 clamped to 1..4,  */
+                          /* or the DG_STREAMS value)                                   */
 } dg_options;
 
 typedef struct {

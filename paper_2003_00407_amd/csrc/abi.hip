@@ -40,7 +40,8 @@ constexpr int kMaxGroups = 8;
 std::vector<int> split_groups(int n_elem, const dg_element_desc* d, const dg_options* opt) {
   int ng = opt ? opt->n_streams : 0;
   if (ng <= 0) {
-    ng = 1;
+    // one group per four elements, at most four (the hardware queues of a process)
+    ng = std::max(1, std::min(4, n_elem / 4));
     if (const char* s = std::getenv("DG_STREAMS")) ng = std::max(1, std::atoi(s));
   }
   ng = std::max(1, std::min({ng, n_elem, kMaxGroups}));
