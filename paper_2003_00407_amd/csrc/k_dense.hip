@@ -1032,8 +1032,13 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
         StridedB pv{reinterpret_cast<unsigned char*>(L + 5 * (size_t)np * R) + slot, R};
         tri_lu(sd, se, m, shf[j], 2.2e-16 * onenorm, ta, tb, tu, tl, pv);
         for (int i = 0; i < m; ++i) z[i] = hash_unit(j, i);
-        for (int it = 0; it < 4; ++it) {
+        // an isolated eigenvalue needs no re-orthogonalisation: two solves (growth
+        // at most ~1/(eps ||T||) each, far from overflow), one normalisation
+        const bool single = cst[j] == j && (j + 1 >= nwant || cst[j + 1] == j + 1);
+        const int n_it = single ? 2 : 4;
+        for (int it = 0; it < n_it; ++it) {
           tri_solve(m, ta, tb, tu, tl, pv, z);
+          if (single && it + 1 < n_it) continue;
           for (int q = cst[j]; q < j; ++q) {
             const double* zq = Zv + (size_t)q * np;
             double dot = 0.0;
