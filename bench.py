@@ -2,17 +2,18 @@
 """Benchmark: batched ALB generation on one MI355X.
 
 One step = the whole hot path on one batch: seeded cold start -> LOBPCG to a
-residual of 1e-8 Ha on every element -> ALBs (restriction + SVD
-orthonormalisation), for the 4x4 graphene-like slab (16 extended elements of
-48x48x64, 40 states each, FP64).  The mixed-precision path (FP32 H*psi and
-subspace GEMMs, FP64 small dense and refinement) is timed on the same batch
-and reported beside it.
+residual of 1e-8 Ha on every element -> ALBs (restriction + orthonormalisation),
+for the 4x4 graphene-like slab (16 extended elements of 48x48x64, 40 states
+each, FP64).  The mixed-precision path (FP32 stage, FP64 refinement) is timed
+on the same batch and reported beside it, and so is a pass with all elements in
+one stream (kernel durations without overlap).
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,10 +21,27 @@ import time
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector / matrix
-FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
 CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
+# kernel symbol of each timing class's main kernel (rocprofv3 names)
+CLASS_KERNEL = {"plane": "k_plane", "zcol": "k_zcol", "nonlocal": "k_nl_", "teter": "k_plane",
+                "gram": "k_gram", "rotate": "k_rotate", "rayleigh_ritz": "k_rr_lds", "other": "k_residual"}
+
+# HBM bytes per launch from `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of
+# `bench.py --steps 1 --warmup 0 --no-mixed --no-isolated --no-cpu-baseline --copy-probe-mib 1024`
+# on the C2 batch, scaled by what the counters read for the 1 GiB device copy of the same
+# run (profiles/c2_fp64_hbm_traffic.md).  Valid only for the kernel source they were taken
+# on: `traffic` is reported null once the file's SHA-256 differs.
+PMC_TRAFFIC = {
+    "rayleigh_ritz": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
+                      "sha256": "c594f7fe67327f9776115ee27a812d50724654f98b959c4732379b58fe441bea",
+                      "bytes_per_launch": 4032989},
+    "rotate": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
+               "sha256": "c594f7fe67327f9776115ee27a812d50724654f98b959c4732379b58fe441bea",
+               "bytes_per_launch": 720559495},
+}
 
 
 def parse():
@@ -34,6 +52,7 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-isolated", action="store_true", help="skip the one-stream pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle LOBPCG iterations in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -41,7 +60,7 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(E, D, x0, precision, steps, warmup, tol, torch):
+def run_path(E, x0, precision, steps, warmup, tol, torch):
     """Warm up, then time `steps` full solves + ALBs; returns timing and kernel stats."""
     for _ in range(warmup):
         E.solve(x0, precision=precision, tol=tol)
@@ -51,14 +70,14 @@ def run_path(E, D, x0, precision, steps, warmup, tol, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = None
-    st = 0
+    res = None
     for _ in range(steps):
         eig, res, iters, st = E.solve(x0, precision=precision, tol=tol)
         E.make_alb()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, launches, work = E.timing(enable=False, reset=True)
-    return {"seconds": t1 - t0, "iters": iters, "status": st, "ms": ms, "launches": launches,
+    return {"seconds": t1 - t0, "iters": iters, "ms": ms, "launches": launches,
             "work": work, "max_resid": float(res.max().item())}
 
 
@@ -79,8 +98,13 @@ def kernel_table(r):
     return tab
 
 
-def roofline_for(r, prec_bytes):
-    """Roofline of the dominant kernel class over the timed region."""
+def source_sha(path):
+    with open(os.path.join(HERE, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def roofline_for(r, config):
+    """Roofline of the dominant kernel class (most GPU time) over the timed region."""
     i = int(np.argmax(r["ms"]))
     name = CLASSES[i]
     ms, n, w = r["ms"][i], max(1, r["launches"][i]), r["work"][i]
@@ -88,18 +112,23 @@ def roofline_for(r, prec_bytes):
     if i <= 3:       # HBM-bound passes: algorithmic bytes per launch / duration
         achieved = (w / n) / avg_s / 1e9
         peak, unit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
-    elif i <= 5:     # GEMMs on FP64 MFMA: algorithmic flops per launch / duration
+    elif i <= 5:     # subspace GEMMs on FP64 MFMA: algorithmic flops per launch / duration
         achieved = (w / n) / avg_s / 1e12
         peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "mfma"
-    else:            # small dense FP64 (one workgroup per element): vector ALU
+    else:            # small dense FP64, one workgroup per element: vector ALU
         achieved = (w / n) / avg_s / 1e12
         peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "alu"
-    return {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "avg_launch_us": round(avg_s * 1e6, 2), "launches": int(n)}
+    traffic = None
+    t = PMC_TRAFFIC.get(name)
+    if t and t["config"] == config and source_sha(t["source"]) == t["sha256"]:
+        traffic = t["bytes_per_launch"]
+    return {"kernel": name, "symbol": CLASS_KERNEL[name], "bound": bound, "achieved": round(achieved, 4),
+            "peak": peak, "unit": unit, "frac": round(achieved / peak, 5), "traffic": traffic,
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches": int(n),
+            "work_per_launch": w / n}
 
 
-def hpsi_rate(r, prec_bytes):
+def hpsi_rate(r):
     """H*psi GB/s: algorithmic bytes of the H*psi passes over their summed time."""
     ms = r["ms"][0] + r["ms"][1] + r["ms"][2]
     by = r["work"][0] + r["work"][1] + r["work"][2]
@@ -126,6 +155,14 @@ def cpu_baseline(cfg, n_iters_scale, cpu_iters):
                        f"GPU needed for that element to reach 1e-8 (ALB SVD time negligible)")}
 
 
+def make_x0(cfg, E, D, torch):
+    if cfg.name == "c4":
+        # 2.3e9 starting values: drawn on the device from a seeded generator
+        gen = torch.Generator(device="cuda").manual_seed(cfg.x0_seed_base)
+        return torch.randn(int(E.offsets(D.DG_OFF_X0)[-1]), dtype=torch.float64, device="cuda", generator=gen)
+    return torch.tensor(D.pack_initial(cfg.elements, cfg.x0_seed_base), dtype=torch.float64, device="cuda")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,7 +179,7 @@ def main():
     cfg = W.make_config(args.config)
     els = cfg.elements
     E = D.Elements(els)
-    x0 = torch.tensor(D.pack_initial(els, cfg.x0_seed_base), dtype=torch.float64, device="cuda")
+    x0 = make_x0(cfg, E, D, torch)
     if args.copy_probe_mib > 0:
         buf = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
         buf2 = torch.empty_like(buf)
@@ -151,8 +188,8 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] config={cfg.name} elements={len(els)} grid={els[0].n} J={els[0].n_states}",
           file=sys.stderr, flush=True)
-    r64 = run_path(E, D, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch)
-    print(f"[bench] fp64: {r64['seconds']:.3f}s for {args.steps} steps, iters {list(r64['iters'])}",
+    r64 = run_path(E, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch)
+    print(f"[bench] fp64: {r64['seconds']:.3f}s for {args.steps} steps, iters {[int(i) for i in r64['iters']]}",
           file=sys.stderr, flush=True)
     n = len(els)
     value = n * args.steps / r64["seconds"]
@@ -171,22 +208,30 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name + ": " + cfg.description, "n_elem": n,
                    "grid": list(els[0].n), "states": els[0].n_states,
-                   "tol": args.tol, "method": "lobpcg", "precision": "fp64"},
-        "hpsi_GBs_fp64": hpsi_rate(r64, 8),
+                   "tol": args.tol, "method": "lobpcg", "precision": "fp64",
+                   "element_groups": int(os.environ.get("DG_STREAMS", "0")) or max(1, min(4, n // 4))},
+        "hpsi_GBs_fp64": hpsi_rate(r64),
         "iters_fp64": [int(i) for i in r64["iters"]],
         "max_resid_fp64": r64["max_resid"],
         "kernels_fp64": kernel_table(r64),
-        "roofline": roofline_for(r64, 8),
+        "roofline": roofline_for(r64, cfg.name),
     }
     if not args.no_mixed:
-        rmx = run_path(E, D, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch)
+        rmx = run_path(E, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch)
         print(f"[bench] mixed: {rmx['seconds']:.3f}s", file=sys.stderr, flush=True)
         out["mixed"] = {"value": round(n * args.steps / rmx["seconds"], 4),
                         "ms_per_step": round(1000.0 * rmx["seconds"] / args.steps, 3),
                         "speedup_vs_fp64": round(r64["seconds"] / rmx["seconds"], 3),
                         "iters": [int(i) for i in rmx["iters"]], "max_resid": rmx["max_resid"],
-                        "hpsi_GBs_fp32_and_fp64": hpsi_rate(rmx, 4),
                         "kernels": kernel_table(rmx)}
+    if not args.no_isolated:
+        # all elements in one stream: kernel durations without overlap between element groups
+        del E
+        E1 = D.Elements(els, n_streams=1)
+        r1 = run_path(E1, x0, D.DG_FP64, 1, 0, args.tol, torch)
+        print(f"[bench] one stream: {r1['seconds']:.3f}s", file=sys.stderr, flush=True)
+        out["one_stream_fp64"] = {"value": round(n / r1["seconds"], 4), "hpsi_GBs": hpsi_rate(r1),
+                                  "kernels": kernel_table(r1)}
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, int(r64["iters"][5]), args.cpu_iters)
