@@ -55,15 +55,17 @@ def parse():
     ap.add_argument("--no-isolated", action="store_true", help="skip the one-stream pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle LOBPCG iterations in the CPU sample")
+    ap.add_argument("--graph-iters", type=int, default=0,
+                    help="LOBPCG steps captured per HIP graph replay (0: launch per kernel)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (reference for PMC byte counters)")
     return ap.parse_args()
 
 
-def run_path(E, x0, precision, steps, warmup, tol, torch):
+def run_path(E, x0, precision, steps, warmup, tol, torch, graph_iters=0):
     """Warm up, then time `steps` full solves + ALBs; returns timing and kernel stats."""
     for _ in range(warmup):
-        E.solve(x0, precision=precision, tol=tol)
+        E.solve(x0, precision=precision, tol=tol, graph_iters=graph_iters)
         E.make_alb()
     torch.cuda.synchronize()
     E.timing(enable=True, reset=True)
@@ -72,7 +74,7 @@ def run_path(E, x0, precision, steps, warmup, tol, torch):
     iters = None
     res = None
     for _ in range(steps):
-        eig, res, iters, st = E.solve(x0, precision=precision, tol=tol)
+        eig, res, iters, st = E.solve(x0, precision=precision, tol=tol, graph_iters=graph_iters)
         E.make_alb()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -188,7 +190,7 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] config={cfg.name} elements={len(els)} grid={els[0].n} J={els[0].n_states}",
           file=sys.stderr, flush=True)
-    r64 = run_path(E, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch)
+    r64 = run_path(E, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch, args.graph_iters)
     print(f"[bench] fp64: {r64['seconds']:.3f}s for {args.steps} steps, iters {[int(i) for i in r64['iters']]}",
           file=sys.stderr, flush=True)
     n = len(els)
@@ -208,7 +210,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name + ": " + cfg.description, "n_elem": n,
                    "grid": list(els[0].n), "states": els[0].n_states,
-                   "tol": args.tol, "method": "lobpcg", "precision": "fp64",
+                   "tol": args.tol, "method": "lobpcg", "precision": "fp64", "graph_iters": args.graph_iters,
                    "element_groups": int(os.environ.get("DG_STREAMS", "0")) or max(1, min(4, n // 4))},
         "hpsi_GBs_fp64": hpsi_rate(r64),
         "iters_fp64": [int(i) for i in r64["iters"]],
@@ -217,7 +219,7 @@ def main():
         "roofline": roofline_for(r64, cfg.name),
     }
     if not args.no_mixed:
-        rmx = run_path(E, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch)
+        rmx = run_path(E, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch, args.graph_iters)
         print(f"[bench] mixed: {rmx['seconds']:.3f}s", file=sys.stderr, flush=True)
         out["mixed"] = {"value": round(n * args.steps / rmx["seconds"], 4),
                         "ms_per_step": round(1000.0 * rmx["seconds"] / args.steps, 3),

@@ -106,6 +106,10 @@ typedef struct {
   int32_t cheb_degree; /* DG_CHFSI filter degree m                                    */
   const double *x0_dev;/* packed initial blocks, N_k x (J_k + guards) per element     */
                        /* (dg_query_offsets(DG_OFF_X0)); need not be orthonormal      */
+  int32_t graph_iters; /* FP64 LOBPCG: > 0 captures this many iterations of every     */
+                       /* element group as one HIP graph, replayed with one host      */
+                       /* convergence check per replay (the count may then overshoot */
+                       /* max_iter by less than graph_iters); 0: launch per kernel     */
 } dg_solve_params;
 
 enum dg_offset_kind {

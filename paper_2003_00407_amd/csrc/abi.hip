@@ -74,7 +74,7 @@ struct dg_ctx {
   std::vector<Ctx> g;            // one solver context per group
   std::vector<int> lo;           // group element ranges [lo[i], lo[i+1])
   hipStream_t user = nullptr;    // the caller's stream
-  std::vector<hipStream_t> own;  // library streams (groups > 1)
+  std::vector<hipStream_t> own;  // library streams, one per group
   hipEvent_t fork_ev = nullptr;
   std::vector<hipEvent_t> join_ev;
   std::vector<int64_t> off[6];   // batch-wide packed offsets per dg_offset_kind
@@ -232,7 +232,9 @@ int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* 
     b->user = (hipStream_t)hip_stream;
     DG_HIP(hipGetDevice(&b->device));
     const int ng = (int)b->lo.size() - 1;
-    if (ng > 1) {
+    {
+      // every group runs on a library stream (a capturable one even when the caller
+      // passes the legacy default stream)
       DG_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
       for (int i = 0; i < ng; ++i) {
         hipStream_t s;
@@ -259,7 +261,7 @@ int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* 
       }
       Ctx* c = nullptr;
       st = dg::create(&c, n, elems + b->lo[i], opt, (char*)dev_arena + used, arena_bytes - used,
-                      ng > 1 ? (void*)b->own[i] : hip_stream);
+                      (void*)b->own[i]);
       if (st < 0) return st;
       worst = std::max(worst, st);
       b->g.push_back(std::move(*c));

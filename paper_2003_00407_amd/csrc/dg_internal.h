@@ -125,6 +125,8 @@ struct Ctx {
   int* dev_active = nullptr;       // per element solver flags
   int* dev_status = nullptr;       // per element RR status
   int* dev_count = nullptr;        // [active count, NaN count]
+  int* dev_iters = nullptr;        // per element iterations performed (counted by the check kernel)
+  bool capturing = false;          // a stream capture is open: no timing events
   double* dev_maxres = nullptr;    // per element max residual
   double* dev_bounds = nullptr;    // band energy: (a, b, a0) per element
   double* dev_de = nullptr;        // band energy backward: dE per element
@@ -137,6 +139,7 @@ struct Ctx {
   long long* dev_off_grid = nullptr;
   long long* dev_off_eig = nullptr;
   std::vector<int> host_ints;      // staging for small async uploads
+  std::vector<int> host_ints2;      // staging of the iteration-counter reset
   std::vector<int> active_host;    // host mirror of the solver's active flags (work accounting)
   std::vector<double> nnz;         // projector nonzeros per element
   int roles_x = 0;                 // physical block holding the converged X
@@ -211,6 +214,7 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active);
 int launch_rotate(Ctx& c, int prec, const RotArgs& a);
 int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int* active);
 int launch_check(Ctx& c, int* active, double tol);
+void init_kernel_attributes();
 int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                      long long out_off, int rows_e, int sym);
 int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed);

@@ -1287,7 +1287,7 @@ __global__ void __launch_bounds__(256) k_residual(ResArgs A) {
 
 // per element: active = max_{i<J} res_i > tol ; count of active elements
 __global__ void k_check(const ElemDev* elems, int n_elem, int* active, double tol, int* count,
-                        double* maxres) {
+                        double* maxres, int* iter_count) {
   __shared__ double sh[16];
   for (int e = 0; e < n_elem; ++e) {
     const ElemDev& E = elems[e];
@@ -1303,6 +1303,7 @@ __global__ void k_check(const ElemDev* elems, int n_elem, int* active, double to
       }
       if (!(m == m)) active[e] = -1;   // NaN
       maxres[e] = m;
+      if (iter_count && active[e] > 0) ++iter_count[e];
     }
     __syncthreads();
   }
@@ -1461,6 +1462,27 @@ static bool set_lds_limit(const void* fn, int bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
 }
 
+// dynamic-LDS limits of every kernel variant, set once before any launch (and so
+// never from inside a stream capture)
+void init_kernel_attributes() {
+  static const bool done = [] {
+#define DG_GRAM_ATTR(MB)                                    \
+  set_lds_limit((const void*)k_gram<double, MB>, 96000); \
+  set_lds_limit((const void*)k_gram<float, MB>, 96000);
+    DG_GRAM_ATTR(1)
+    DG_GRAM_ATTR(2)
+    DG_GRAM_ATTR(3)
+    DG_GRAM_ATTR(4)
+    DG_GRAM_ATTR(6)
+    DG_GRAM_ATTR(8)
+#undef DG_GRAM_ATTR
+    set_lds_limit((const void*)k_rr_lds, kRRLdsBytes);
+    set_lds_limit((const void*)k_rr, 146000);
+    return true;
+  }();
+  (void)done;
+}
+
 static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                      long long out_off, const int* active, int rows_e, int sym) {
   int ks, kt, maxN, maxE;
@@ -1504,12 +1526,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
 #define DG_GRAM_CASE(MB)                                                                   \
   case MB:                                                                                 \
     if (prec == DG_FP64) {                                                                 \
-      static const bool attr = set_lds_limit((const void*)k_gram<double, MB>, 96000);      \
-      (void)attr;                                                                          \
       hipLaunchKernelGGL((k_gram<double, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);   \
     } else {                                                                               \
-      static const bool attr = set_lds_limit((const void*)k_gram<float, MB>, 96000);       \
-      (void)attr;                                                                          \
       hipLaunchKernelGGL((k_gram<float, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);    \
     }                                                                                      \
     break;
@@ -1553,11 +1571,6 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
   const size_t lds_bytes = (size_t)npmax * npmax * sizeof(double);
   // static LDS of k_rr is ~16.5 KB; 146,000 B of dynamic LDS keeps the total under 160 KB
   const bool use_lds = lds_bytes <= 146000;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_rr, hipFuncAttributeMaxDynamicSharedMemorySize, 146000);
-    attr_set = true;
-  }
   // algorithmic flop estimate: Cholesky + inverse (n^3/3 each), two n^3 products,
   // tridiagonalisation (4n^3/3), back-transformation and coefficients (4 n^2 k)
   double flops = 0.0;
@@ -1586,8 +1599,6 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
     return DG_ERR_SHAPE;
   }
   if (lds_gen) {
-    static const bool attr = set_lds_limit((const void*)k_rr_lds, kRRLdsBytes);
-    (void)attr;
     hipLaunchKernelGGL(k_rr_lds, dim3(c.n_elem), dim3(kRRThreads), kRRLdsBytes, c.stream, a);
   } else {
     hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
@@ -1641,7 +1652,7 @@ int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int
 
 int launch_check(Ctx& c, int* active, double tol) {
   hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, c.stream, c.elems_dev, c.n_elem, active, tol,
-                     c.dev_count, c.dev_maxres);
+                     c.dev_count, c.dev_maxres, c.dev_iters);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

@@ -29,14 +29,14 @@ static hipEvent_t get_event(Ctx& c) {
 }
 
 TimedScope::TimedScope(Ctx& ctx, int k, double w) : c(ctx), cls(k), work(w) {
-  if (!c.timing) return;
+  if (!c.timing || c.capturing) return;
   a = get_event(c);
   b = get_event(c);
   if (a) hipEventRecord(a, c.stream);
 }
 
 TimedScope::~TimedScope() {
-  if (!c.timing || !a || !b) return;
+  if (!c.timing || c.capturing || !a || !b) return;
   hipEventRecord(b, c.stream);
   c.pending.push_back({cls, a, b});
   c.tacc.work[cls] += work;
@@ -134,7 +134,8 @@ struct ElemPlan {
 
 struct Plan {
   std::vector<ElemPlan> el;
-  size_t off_elems, off_iota, off_active, off_status, off_count, off_maxres, off_phase, off_bounds, off_de,
+  size_t off_elems, off_iota, off_active, off_status, off_count, off_iters, off_maxres, off_phase, off_bounds,
+      off_de,
       off_minpiv;
   int n_extra;
   size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_lists;
@@ -253,6 +254,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_active = take(sizeof(int) * n_elem);
   P.off_status = take(sizeof(int) * n_elem);
   P.off_count = take(sizeof(int) * 4);
+  P.off_iters = take(sizeof(int) * n_elem);
   P.off_phase = take(sizeof(long long) * 8 * n_elem);
   P.off_maxres = take(sizeof(double) * n_elem);
   P.off_bounds = take(sizeof(double) * 3 * n_elem);
@@ -333,6 +335,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
     set_error("arena too small: need " + std::to_string(P.total) + " bytes");
     return DG_ERR_OOM;
   }
+  init_kernel_attributes();
   Ctx* c = new Ctx();
   c->stream = (hipStream_t)stream;
   c->n_elem = n_elem;
@@ -521,6 +524,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->dev_active = (int*)(A + P.off_active);
   c->dev_status = (int*)(A + P.off_status);
   c->dev_count = (int*)(A + P.off_count);
+  c->dev_iters = (int*)(A + P.off_iters);
   c->dev_bounds = (double*)(A + P.off_bounds);
   c->dev_de = (double*)(A + P.off_de);
   c->dev_minpiv = (double*)(A + P.off_minpiv);

@@ -100,7 +100,8 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   return launch_permute(c, perm, active);
 }
 
-static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done, bool carry_p = false) {
+static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done, bool carry_p = false,
+                      int graph_iters = 0) {
   int st;
   int* active = c.dev_active;
   // an FP32 stage stops an element once its residual stops improving (FP32 floor)
@@ -114,6 +115,12 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
   c.active_host.assign(c.n_elem, 1);
+  {
+    std::vector<int> zeros(c.n_elem, 0);
+    c.host_ints2 = zeros;
+    DG_HIP(hipMemcpyAsync(c.dev_iters, c.host_ints2.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice,
+                          c.stream));
+  }
   // Gram matrices of FP32 blocks are accurate to ~1e-7: treat smaller scaled pivots as breakdown.
   // W/P columns whose scaled pivot is below drop_tol leave the basis: the projected
   // matrix is then accurate to about eps * ||H|| / drop_tol in the worst kept direction.
@@ -127,11 +134,62 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     if ((st = launch_hpsi(c, -1, 0, prec, B_P, B_HP, active))) return st;
     have_p = true;
   }
-  std::vector<int> it_elem(c.n_elem, 0);
   int it = 0;
+  // one LOBPCG step after a convergence check: W = T(R), W -= X (X^T W), H W, then the
+  // projected problem on S = [X W P] and the rotations (Eqs. (2)-(4), steps 3-7)
+  auto step = [&](int nb) -> int {
+    int s2;
+    // W = T(HX - X Theta)  (Eq. (3), step 3)
+    if ((s2 = launch_teter(c, prec, B_X, B_HX, B_W, 0, active))) return s2;
+    // W <- W - X (X^T W)
+    {
+      ColSet SX{1, {B_X, 0, 0}}, SW{1, {B_W, 0, 0}};
+      if ((s2 = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active, 0))) return s2;
+      RotArgs ra{};
+      ra.active = active;
+      ra.S = SX;
+      ra.kS = KC_K;
+      ra.nout = 1;
+      ra.out_blk[0] = B_W;
+      ra.c0[0] = 0;
+      ra.c1[0] = 1;
+      ra.beta[0] = 1.0;
+      ra.alpha = -1.0;
+      ra.c_off = small_code(2);
+      ra.ncol = KC_K;
+      ra.c_blockrows = 1;
+      if ((s2 = launch_rotate(c, prec, ra))) return s2;
+    }
+    // H W
+    if ((s2 = launch_hpsi(c, -1, 0, prec, B_W, B_HW, active))) return s2;
+    // S = [X, W, P], projected problem (Eq. (4)), rotations (Eq. (2))
+    return rr_and_rotate(c, prec, nb, active, true);
+  };
+  // captured mode: after the first step, graph_iters steps (each followed by the
+  // residual and convergence check, which retires converged elements on the device)
+  // are one graph; the host reads the counts once per replay
+  struct GraphHold {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void release() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
+    ~GraphHold() { release(); }
+  } gh;
+  hipGraphExec_t& gexec = gh.exec;
+  hipGraph_t& graph = gh.graph;
+  auto release_graph = [&]() { gh.release(); };
+  const bool use_graph = graph_iters > 0 && !stagnation_exit && c.log_level == 0;
+  bool checked = false;   // a graph replay ended with the residual and check
   for (it = 1; it <= max_iter; ++it) {
-    if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
-    if ((st = launch_check(c, active, tol))) return st;
+    if (!checked) {
+      if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
+      if ((st = launch_check(c, active, tol))) return st;
+    }
+    checked = false;
     int cnt[2];
     if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
     if (cnt[1] > 0) {
@@ -141,8 +199,6 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     {
       std::vector<int> act(c.n_elem);
       if ((st = sync_read(c, act.data(), active, sizeof(int) * c.n_elem))) return st;
-      for (int e = 0; e < c.n_elem; ++e)
-        if (act[e] > 0) it_elem[e] = it;
       if (stagnation_exit) {
         std::vector<double> mr(c.n_elem);
         if ((st = sync_read(c, mr.data(), c.dev_maxres, sizeof(double) * c.n_elem))) return st;
@@ -196,31 +252,42 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
       }
     }
     if (cnt[0] == 0) break;
-    // W = T(HX - X Theta)  (Eq. (3), step 3)
-    if ((st = launch_teter(c, prec, B_X, B_HX, B_W, 0, active))) return st;
-    // W <- W - X (X^T W)
-    {
-      ColSet SX{1, {B_X, 0, 0}}, SW{1, {B_W, 0, 0}};
-      if ((st = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active, 0))) return st;
-      RotArgs ra{};
-      ra.active = active;
-      ra.S = SX;
-      ra.kS = KC_K;
-      ra.nout = 1;
-      ra.out_blk[0] = B_W;
-      ra.c0[0] = 0;
-      ra.c1[0] = 1;
-      ra.beta[0] = 1.0;
-      ra.alpha = -1.0;
-      ra.c_off = small_code(2);
-      ra.ncol = KC_K;
-      ra.c_blockrows = 1;
-      if ((st = launch_rotate(c, prec, ra))) return st;
+    if (use_graph && have_p) {
+      if (!gexec) {
+        c.capturing = true;
+        hipError_t ce = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal);
+        int s3 = ce == hipSuccess ? DG_OK : DG_ERR_HIP;
+        for (int g = 0; g < graph_iters && s3 == DG_OK; ++g) {
+          s3 = step(3);
+          if (s3 == DG_OK) s3 = launch_residual(c, prec, B_X, B_HX, 0, active);
+          if (s3 == DG_OK) s3 = launch_check(c, active, tol);
+        }
+        hipError_t ee = ce == hipSuccess ? hipStreamEndCapture(c.stream, &graph) : ce;
+        c.capturing = false;
+        if (s3 != DG_OK) return s3;
+        if (ee != hipSuccess) {
+          set_error(std::string("stream capture: ") + hipGetErrorString(ee));
+          return DG_ERR_HIP;
+        }
+        if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+          release_graph();
+          set_error("hipGraphInstantiate failed");
+          return DG_ERR_HIP;
+        }
+      }
+      {
+        TimedScope ts(c, TC_OTHER);
+        if (hipGraphLaunch(gexec, c.stream) != hipSuccess) {
+          release_graph();
+          set_error("hipGraphLaunch failed");
+          return DG_ERR_HIP;
+        }
+      }
+      it += graph_iters - 1;
+      checked = true;
+      continue;
     }
-    // H W
-    if ((st = launch_hpsi(c, -1, 0, prec, B_W, B_HW, active))) return st;
-    // S = [X, W, P], projected problem (Eq. (4)), rotations (Eq. (2))
-    if ((st = rr_and_rotate(c, prec, have_p ? 3 : 2, active, true))) return st;
+    if ((st = step(have_p ? 3 : 2))) return st;
     have_p = true;
   }
   c.active_host.clear();
@@ -230,12 +297,13 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     c.host_ints = ones;
     DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   }
+  release_graph();
+  // iterations per element (counted by the check kernel before the final check)
+  if (iters && (st = sync_read(c, iters, c.dev_iters, sizeof(int) * c.n_elem))) return st;
   if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
   if ((st = launch_check(c, active, tol))) return st;
   int cnt[2];
   if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
-  if (iters)
-    for (int e = 0; e < c.n_elem; ++e) iters[e] = it_elem[e];
   *n_done = c.n_elem - cnt[0];
   return cnt[1] > 0 ? DG_ERR_NUMERIC : DG_OK;
 }
@@ -268,7 +336,8 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
   int done = 0;
   if (p->precision == DG_FP64) {
     if ((st = launch_copy_packed(c, DG_FP64, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
-    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it1.data(), &done)
+    st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it1.data(), &done, false,
+                                             std::max(0, p->graph_iters))
                                 : run_chfsi(c, DG_FP64, p->tol, p->max_iter, p->cheb_degree, it1.data(), &done);
     if (st < 0) return st;
   } else {
@@ -287,7 +356,7 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
       int perm[kMaxBlocks] = {B_W, B_X, B_P, B_HX, B_HW, B_HP, B_T0, B_T1};
       if ((st = launch_permute(c, perm, nullptr))) return st;
     }
-    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry);
+    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry, std::max(0, p->graph_iters));
     if (st < 0) return st;
   }
   c.solved = true;

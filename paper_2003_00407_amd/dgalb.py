@@ -50,7 +50,7 @@ class Options(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
                 ("tol_mixed", C.c_double), ("max_iter", C.c_int32), ("cheb_degree", C.c_int32),
-                ("x0_dev", C.c_void_p)]
+                ("x0_dev", C.c_void_p), ("graph_iters", C.c_int32)]
 
 
 _lib.dg_status_string.restype = C.c_char_p
@@ -192,7 +192,7 @@ class Elements:
         return y
 
     def solve(self, x0, method: int = DG_LOBPCG, precision: int = DG_FP64, tol: float = 1e-8,
-              tol_mixed: float = 1e-4, max_iter: int = 300, cheb_degree: int = 16):
+              tol_mixed: float = 1e-4, max_iter: int = 300, cheb_degree: int = 16, graph_iters: int = 0):
         """Lowest J_k eigenpairs of every element; returns (eig, resid, iters, status)."""
         torch = self.torch
         if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
@@ -201,7 +201,8 @@ class Elements:
         eig = self._dev(n_eig, torch.float64)
         res = self._dev(n_eig, torch.float64)
         iters = (C.c_int32 * self.n_elem)()
-        p = SolveParams(method, precision, tol, tol_mixed, max_iter, cheb_degree, C.c_void_p(x0.data_ptr()))
+        p = SolveParams(method, precision, tol, tol_mixed, max_iter, cheb_degree, C.c_void_p(x0.data_ptr()),
+                        graph_iters)
         st = _check(_lib.dg_solve_elements(self.ctx, C.byref(p), C.c_void_p(eig.data_ptr()),
                                            C.c_void_p(res.data_ptr()), iters), "dg_solve_elements")
         return eig, res, np.array(list(iters), dtype=np.int32), st

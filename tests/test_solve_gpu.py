@@ -171,3 +171,29 @@ def test_element_groups_on_streams():
     y1 = E1.apply_H(x, 3).cpu().numpy()
     y3 = E3.apply_H(x, 3).cpu().numpy()
     assert np.max(np.abs(y1 - y3)) <= 1e-12 * np.max(np.abs(y1))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_captured_graph_iterations(precision):
+    """LOBPCG steps captured as one HIP graph per element group and replayed (four
+    steps per replay, one host check per replay): same eigenpairs as launching each
+    kernel, iteration counts at most three steps longer."""
+    torch = need_torch_cuda()
+    from paper_2003_00407_amd import dgalb as D
+    els = W.small_slab(n_states=8)
+    x0 = torch.tensor(D.pack_initial(els, 100), dtype=torch.float64, device="cuda")
+    E = D.Elements(els)
+    eig0, res0, it0, st0 = E.solve(x0, precision=precision, tol=1e-9)
+    X0 = E.vectors().cpu().numpy()
+    eig1, res1, it1, st1 = E.solve(x0, precision=precision, tol=1e-9, graph_iters=4)
+    X1 = E.vectors().cpu().numpy()
+    print(f"[graph] prec={precision} iterations eager {it0.tolist()} graph {it1.tolist()}", flush=True)
+    assert st0 == 0 and st1 == 0
+    assert res1.max().item() <= 1e-9
+    assert torch.max(torch.abs(eig0 - eig1)).item() < 1e-10
+    assert np.all(it1 >= it0) and np.all(it1 - it0 <= 3)
+    off = E.offsets(D.DG_OFF_VEC)
+    for k, el in enumerate(els):
+        a = X0[off[k]:off[k + 1]].reshape(el.n_states, el.npts).T
+        b = X1[off[k]:off[k + 1]].reshape(el.n_states, el.npts).T
+        assert oalb.max_principal_angle(a, b) < 1e-6
