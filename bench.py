@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-isolated", action="store_true", help="skip the one-stream pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle LOBPCG iterations in the CPU sample")
+    ap.add_argument("--method", default="lobpcg", choices=["lobpcg", "chfsi"])
+    ap.add_argument("--cheb-degree", type=int, default=16)
     ap.add_argument("--graph-iters", type=int, default=0,
                     help="LOBPCG steps captured per HIP graph replay (0: launch per kernel)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -62,10 +64,11 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(E, x0, precision, steps, warmup, tol, torch, graph_iters=0):
+def run_path(E, x0, precision, steps, warmup, tol, torch, graph_iters=0, method=0, degree=16):
     """Warm up, then time `steps` full solves + ALBs; returns timing and kernel stats."""
+    kw = dict(precision=precision, tol=tol, graph_iters=graph_iters, method=method, cheb_degree=degree)
     for _ in range(warmup):
-        E.solve(x0, precision=precision, tol=tol, graph_iters=graph_iters)
+        E.solve(x0, **kw)
         E.make_alb()
     torch.cuda.synchronize()
     E.timing(enable=True, reset=True)
@@ -74,7 +77,7 @@ def run_path(E, x0, precision, steps, warmup, tol, torch, graph_iters=0):
     iters = None
     res = None
     for _ in range(steps):
-        eig, res, iters, st = E.solve(x0, precision=precision, tol=tol, graph_iters=graph_iters)
+        eig, res, iters, st = E.solve(x0, **kw)
         E.make_alb()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -190,7 +193,9 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] config={cfg.name} elements={len(els)} grid={els[0].n} J={els[0].n_states}",
           file=sys.stderr, flush=True)
-    r64 = run_path(E, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch, args.graph_iters)
+    meth = D.DG_LOBPCG if args.method == "lobpcg" else D.DG_CHFSI
+    r64 = run_path(E, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch, args.graph_iters, meth,
+                   args.cheb_degree)
     print(f"[bench] fp64: {r64['seconds']:.3f}s for {args.steps} steps, iters {[int(i) for i in r64['iters']]}",
           file=sys.stderr, flush=True)
     n = len(els)
@@ -210,7 +215,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name + ": " + cfg.description, "n_elem": n,
                    "grid": list(els[0].n), "states": els[0].n_states,
-                   "tol": args.tol, "method": "lobpcg", "precision": "fp64", "graph_iters": args.graph_iters,
+                   "tol": args.tol, "method": args.method, "precision": "fp64", "graph_iters": args.graph_iters,
                    "element_groups": int(os.environ.get("DG_STREAMS", "0")) or max(1, min(4, n // 4))},
         "hpsi_GBs_fp64": hpsi_rate(r64),
         "iters_fp64": [int(i) for i in r64["iters"]],
@@ -219,7 +224,8 @@ def main():
         "roofline": roofline_for(r64, cfg.name),
     }
     if not args.no_mixed:
-        rmx = run_path(E, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch, args.graph_iters)
+        rmx = run_path(E, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch, args.graph_iters, meth,
+                       args.cheb_degree)
         print(f"[bench] mixed: {rmx['seconds']:.3f}s", file=sys.stderr, flush=True)
         out["mixed"] = {"value": round(n * args.steps / rmx["seconds"], 4),
                         "ms_per_step": round(1000.0 * rmx["seconds"] / args.steps, 3),

@@ -235,6 +235,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave sum with DPP row operations and lane reads (no LDS permutes); every lane of
+// the wave must be active.  Within each row of 16 lanes: xor-1 and xor-2 quad
+// permutes, then the half-row and row mirrors; the four row sums are then read
+// from lanes 0, 16, 32, 48 and added in a fixed order (result uniform).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
 // sum over the block, result broadcast to every thread (fixed order)
 __device__ double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -281,6 +304,7 @@ struct RRArgs {
   double drop_tol;       // W/P columns whose scaled pivot is below this are left out of the basis
   double* minpiv;        // optional: smallest scaled pivot, its column, dropped count (diagnostics)
   double ortol;          // eigenvalues closer than ortol * ||T|| are treated as one cluster
+  int lds_dyn;           // k_rr_lds: dynamic LDS bytes of the launch
 };
 
 constexpr int kRRThreads = 512;
@@ -689,8 +713,10 @@ __global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
 // The LDS region is reused phase by phase; G keeps Z, Vm the scaled A and then
 // the packed reflectors, Um the eigenvectors of T between phases.
 // ---------------------------------------------------------------------------
-constexpr int kRRLdsBytes = 146000;
-constexpr int kRRLdsOrder = 134;   // np * np doubles fit in kRRLdsBytes
+constexpr int kLdsPerCU = 163840;                 // 160 KB of LDS per compute unit
+constexpr int kRRStaticLds = 21504;               // bound on k_rr_lds's static LDS
+constexpr int kRRLdsBytes = kLdsPerCU - kRRStaticLds;
+constexpr int kRRLdsOrder = 132;                  // np * np doubles fit in kRRLdsBytes
 
 __device__ __forceinline__ int refl_off(int kk, int m) { return kk * (m - 1) - kk * (kk - 1) / 2; }
 
@@ -826,7 +852,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       const double* zi = L + i * np;
       double t = 0.0;
       for (int k = i + lane; k < j; k += 64) t += zi[k] * vs[k];
-      t = wave_sum(t);
+      t = wave_sum_dpp(t);
       if (lane == 0) ps[i] = -ajj * t;
     }
     __syncthreads();
@@ -913,6 +939,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   // ---- Householder tridiagonalisation in LDS; reflector kk kept in column kk below the diagonal
   const int m = n;
   __shared__ int skip;
+  __shared__ double pq[2][kTriMax];
   for (int kk = 0; kk < m - 2; ++kk) {
     const int mr = m - kk - 1;
     if (wv == 0) {
@@ -922,7 +949,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
         const double x = L[(kk + 1 + i) * np + kk];
         part += x * x;
       }
-      const double ss = wave_sum(part);
+      const double ss = wave_sum_dpp(part);
       const double x0 = L[(kk + 1) * np + kk];
       const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
       const double vv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
@@ -938,19 +965,27 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     __syncthreads();
     if (skip) continue;
     const double tau = stau[kk];
-    // p = tau A v: one wave per row, lanes along the row
-    for (int i = wv; i < mr; i += nw) {
-      const double* row = L + (kk + 1 + i) * np + kk + 1;
-      double acc = 0.0;
-      for (int j = lane; j < mr; j += 64) acc += row[j] * vs[j];
-      acc = wave_sum(acc);
-      if (lane == 0) ps[i] = tau * acc;
+    // p = tau A v; A is symmetric, so row i is read as column i (consecutive threads,
+    // consecutive addresses): two threads per row, each over half of the rows
+    {
+      const int q = tid >> 8, qn = (mr + 1) >> 1;
+      const int j0 = q * qn, j1 = min(mr, j0 + qn);
+      for (int i = tid & 255; i < mr; i += 256) {
+        const double* col = L + (kk + 1) * np + kk + 1 + i;
+        double acc = 0.0;
+        for (int j = j0; j < j1; ++j) acc += col[j * np] * vs[j];
+        pq[q][i] = acc;
+      }
     }
     __syncthreads();
     if (wv == 0) {
       double kp = 0.0;
-      for (int i = lane; i < mr; i += 64) kp += vs[i] * ps[i];
-      const double Kc = 0.5 * tau * wave_sum(kp);
+      for (int i = lane; i < mr; i += 64) {
+        const double p = tau * (pq[0][i] + pq[1][i]);
+        ps[i] = p;
+        kp += vs[i] * p;
+      }
+      const double Kc = 0.5 * tau * wave_sum_dpp(kp);
       for (int i = lane; i < mr; i += 64) ws[i] = ps[i] - Kc * vs[i];
     }
     __syncthreads();
@@ -1017,7 +1052,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   }
   __syncthreads();
   double* Zv = Um;   // eigenvector j of T at Zv[j * np + i]
-  const int R = min(nt, kRRLdsBytes / (np * (5 * (int)sizeof(double) + 1)));
+  const int R = min(nt, A.lds_dyn / (np * (5 * (int)sizeof(double) + 1)));
   // vector slot of this thread: slots spread over the waves (latency hiding)
   const int slot = (lane < (R + nw - 1) / nw) ? lane * nw + wv : R;
   for (int cb = 0; cb < nwant; cb += R) {
@@ -1069,7 +1104,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       const double* zq = zl + q * np;
       double dot = 0.0;
       for (int i = lane; i < m; i += 64) dot += zq[i] * zj[i];
-      dot = wave_sum(dot);
+      dot = wave_sum_dpp(dot);
       if (lane == 0) ps[q] = dot;
     }
     __syncthreads();
@@ -1081,7 +1116,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
         zj[i] = v;
         part += v * v;
       }
-      const double nn = 1.0 / sqrt(wave_sum(part));
+      const double nn = 1.0 / sqrt(wave_sum_dpp(part));
       for (int i = lane; i < m; i += 64) zj[i] *= nn;
     }
     __syncthreads();
@@ -1095,7 +1130,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
       double dot = 0.0;
       for (int i = lane; i < m - 1 - kk; i += 64) dot += v[i] * z[kk + 1 + i];
-      dot = wave_sum(dot) * tau;
+      dot = wave_sum_dpp(dot) * tau;
       for (int i = lane; i < m - 1 - kk; i += 64) z[kk + 1 + i] -= dot * v[i];
     }
   }
@@ -1582,24 +1617,29 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
   }
   // every working matrix in LDS when the orders allow it (always for Cholesky QR)
   bool lds_gen = npmax <= kRRLdsOrder;
+  size_t lds_need = 0;
   if (lds_gen) {
     for (int e = 0; e < c.n_elem; ++e) {
       const int n = mode == RR_GEN ? nb * c.K[e] : (kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
       const int npe = n + (n & 1);
       const int nw = mode == RR_SVD ? n : std::min(nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]), n);
-      if ((size_t)(nw * npe + n * (n - 1) / 2) * sizeof(double) > (size_t)kRRLdsBytes) lds_gen = false;
+      const size_t phase_d = (size_t)(nw * npe + n * (n - 1) / 2) * sizeof(double);
+      const size_t mat = (size_t)npe * npe * sizeof(double);
+      lds_need = std::max({lds_need, phase_d, mat, (size_t)npe * 41});
     }
+    if (lds_need > (size_t)kRRLdsBytes) lds_gen = false;
   }
   RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status, use_lds ? npmax : 0,
            c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
-           c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol};
+           c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol,
+           (int)lds_need};
   TimedScope ts(c, TC_RR, flops);
   if (!lds_gen && mode == RR_CHOLQR) {
     set_error("Cholesky QR of an order above the LDS limit");
     return DG_ERR_SHAPE;
   }
   if (lds_gen) {
-    hipLaunchKernelGGL(k_rr_lds, dim3(c.n_elem), dim3(kRRThreads), kRRLdsBytes, c.stream, a);
+    hipLaunchKernelGGL(k_rr_lds, dim3(c.n_elem), dim3(kRRThreads), lds_need, c.stream, a);
   } else {
     hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
   }
