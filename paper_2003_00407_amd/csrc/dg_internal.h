@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/dg_alb.h"
@@ -147,6 +148,8 @@ struct Ctx {
   long long gram_part_stride = 0;
   int gram_part_ld = 0;
   int gram_max_split = 16;
+  std::map<long long, int> gram_split_table;   // autotuned row splits per Gram shape
+  bool autotune = true;                        // DG_TUNE=0 keeps the default splits
   int nl_pending_np = 0, nl_pending_kk = 0;
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable

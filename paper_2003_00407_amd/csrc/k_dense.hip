@@ -14,6 +14,7 @@
 #include "tridiag.h"
 
 #include <algorithm>
+#include <cstdio>
 
 namespace dg {
 
@@ -1543,8 +1544,14 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     }
   const int cap = 8 * maxb;
   const int groups = (nblk + cap - 1) / cap;
-  int nsplit = std::max(1, std::min(c.gram_max_split, (1024 + groups * c.n_elem - 1) / (groups * c.n_elem)));
-  nsplit = std::min(nsplit, std::max(1, rows / 256));
+  // row-range split: about 1024 workgroups over the launch, at least 256 rows each; the
+  // autotuner below may replace it by half or twice that for this Gram shape
+  const int split_cap = std::max(1, std::min(c.gram_max_split, rows / 256));
+  int nsplit = std::max(1, std::min(split_cap, (1024 + groups * c.n_elem - 1) / (groups * c.n_elem)));
+  const long long key = (((((long long)prec * 1024 + maxni) * 1024 + maxnj) * 2 + sym) * 2 + (same ? 1 : 0)) * 2 +
+                        rows_e;
+  auto tuned = c.gram_split_table.find(key);
+  if (tuned != c.gram_split_table.end()) nsplit = tuned->second;
   GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, rows_e, sym, same ? 1 : 0, cap, c.gram_part,
               c.gram_part_stride, c.gram_part_ld};
   double flops = 0.0;
@@ -1556,8 +1563,9 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     flops += 2.0 * r * (S.nb * ke) * (T.nb * kt);
   }
   const size_t lds = (size_t)GP_R * (nc + 1) * sizeof(double) + (size_t)nc * sizeof(void*);
-  TimedScope ts(c, TC_GRAM, flops);
-  dim3 g1(groups, nsplit, c.n_elem);
+  auto launch = [&](int ns) -> int {
+    ga.nsplit = ns;
+    dim3 g1(groups, ns, c.n_elem);
 #define DG_GRAM_CASE(MB)                                                                   \
   case MB:                                                                                 \
     if (prec == DG_FP64) {                                                                 \
@@ -1566,18 +1574,51 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
       hipLaunchKernelGGL((k_gram<float, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);    \
     }                                                                                      \
     break;
-  switch (maxb) {
-    DG_GRAM_CASE(1)
-    DG_GRAM_CASE(2)
-    DG_GRAM_CASE(3)
-    DG_GRAM_CASE(4)
-    DG_GRAM_CASE(6)
-    DG_GRAM_CASE(8)
-    default:
-      set_error("Gram: unsupported block count");
-      return DG_ERR_SHAPE;
-  }
+    switch (maxb) {
+      DG_GRAM_CASE(1)
+      DG_GRAM_CASE(2)
+      DG_GRAM_CASE(3)
+      DG_GRAM_CASE(4)
+      DG_GRAM_CASE(6)
+      DG_GRAM_CASE(8)
+      default:
+        set_error("Gram: unsupported block count");
+        return DG_ERR_SHAPE;
+    }
 #undef DG_GRAM_CASE
+    return DG_OK;
+  };
+  if (tuned == c.gram_split_table.end() && c.autotune && !c.capturing) {
+    // autotuner: time the candidate splits once each on this launch's data, keep the fastest
+    const int cand[3] = {std::max(1, nsplit / 2), nsplit, std::min(split_cap, nsplit * 2)};
+    float best = 1e30f;
+    int best_ns = nsplit;
+    hipEvent_t ev[2];
+    DG_HIP(hipEventCreate(&ev[0]));
+    DG_HIP(hipEventCreate(&ev[1]));
+    for (int ci = 0; ci < 3; ++ci) {
+      if (ci > 0 && cand[ci] == cand[ci - 1]) continue;
+      DG_HIP(hipEventRecord(ev[0], c.stream));
+      if (int st = launch(cand[ci])) return st;
+      DG_HIP(hipEventRecord(ev[1], c.stream));
+      DG_HIP(hipEventSynchronize(ev[1]));
+      float ms = 0.f;
+      DG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      if (ms < best) {
+        best = ms;
+        best_ns = cand[ci];
+      }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    c.gram_split_table[key] = best_ns;
+    nsplit = best_ns;
+    if (c.log_level > 0)
+      fprintf(stderr, "[dg] gram autotune %dx%d sym=%d prec=%d: split %d (%.3f ms)\n", maxni, maxnj, sym, prec,
+              best_ns, best);
+  }
+  TimedScope ts(c, TC_GRAM, flops);
+  if (int st = launch(nsplit)) return st;
   GramReduceArgs ra{c.elems_dev, active, sym, S.nb, T.nb, kS, kT, nsplit, c.gram_part,
                     c.gram_part_stride, c.gram_part_ld, out_off, 0};
   dim3 g2((maxni * maxnj + 255) / 256, c.n_elem);
