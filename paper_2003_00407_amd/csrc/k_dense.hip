@@ -195,6 +195,151 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gram of FP32 blocks with BF16 matrix cores (the FP32 stage of the mixed path):
+// every FP32 value is split into three BF16 pieces x = x0 + x1 + x2 (24 significant
+// bits), the six products x_a y_b with a + b <= 2 of a 32-row stage are summed by
+// v_mfma_f32_16x16x32_bf16 in FP32, and each stage's sum is added to FP64
+// accumulators.  Same row-panel structure as k_gram: a workgroup stages 32 rows of
+// every column (three BF16 planes, column-major in LDS) and owns all output blocks.
+// v_mfma_f32_16x16x32_bf16 (checked on the device): lane l supplies A[l%16][k] and
+// B[k][l%16] for eight k that A and B share; result register q is D[4(l/16)+q][l%16].
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int GB_R = 32;          // rows per stage (the MFMA's k)
+constexpr int GB_PITCH = 40;      // BF16 per staged column (32 rows + pad)
+
+__device__ __forceinline__ unsigned short bf16_bits_rn(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// PF: staged values per thread and stage (16 columns per pass of the workgroup)
+template <int MAXB, int PF>
+__global__ void __launch_bounds__(GP_THREADS) k_gram_bf16(GramArgs A) {
+  const int e = blockIdx.z;
+  const ElemDev& E = A.elems[e];
+  if (A.active && !A.active[e]) return;
+  const int kS = kcode(A.kS, E);
+  const int kT = kcode(A.kT, E);
+  const int ni = A.S.nb * kS, nj = A.T.nb * kT;
+  const int bi = (ni + 15) >> 4, bj = (nj + 15) >> 4;
+  const int nblk = A.sym ? bi * (bi + 1) / 2 : bi * bj;
+  const int b0 = blockIdx.x * A.cap;
+  if (b0 >= nblk) return;
+  const int split = blockIdx.y;
+  const int nrows = nrows_of(E, A.rows_e);
+  const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GB_R - 1) / GB_R * GB_R;
+  const int r0 = split * rows_per;
+  const int r1 = min(nrows, r0 + rows_per);
+  const int ncS = bi * 16, nc = ncS + (A.same ? 0 : bj * 16);
+  const int toff = A.same ? 0 : ncS;
+  extern __shared__ double gsm[];
+  unsigned short* sm = reinterpret_cast<unsigned short*>(gsm);          // [3][nc][GB_PITCH]
+  const float** cp = reinterpret_cast<const float**>(sm + 3 * nc * GB_PITCH);   // [nc]
+  for (int c = threadIdx.x; c < nc; c += GP_THREADS) {
+    const float* ptr = nullptr;
+    if (c < ncS) {
+      if (c < ni) ptr = vcol<float>(E, A.S, c, kS);
+    } else if (c - ncS < nj) {
+      ptr = vcol<float>(E, A.T, c - ncS, kT);
+    }
+    cp[c] = ptr;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int bp[MAXB], bq[MAXB];
+  bool bv[MAXB];
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t) {
+    const int b = b0 + w + 8 * t;
+    bv[t] = b < nblk && b < b0 + A.cap;
+    int p = 0, q = 0;
+    if (bv[t]) gram_block(b, bi, bj, A.sym, p, q);
+    bp[t] = p;
+    bq[t] = q;
+  }
+  double acc[MAXB][4];
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[t][q] = 0.0;
+  __syncthreads();
+  // staging map: thread -> grid row (tid % 32) of columns tid / 32 + 16 u
+  const int srow = threadIdx.x & (GB_R - 1), scol = threadIdx.x >> 5;
+  float pre[PF];
+  auto load = [&](int rbase) {
+    const int rr = rbase + srow;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int c = scol + 16 * u;
+      float v = 0.f;
+      if (c < nc) {
+        const float* ptr = cp[c];
+        if (ptr && rr < r1) v = ptr[rr];
+      }
+      pre[u] = v;
+    }
+  };
+  const int plane = nc * GB_PITCH;
+  const int koff = 8 * (lane >> 4);
+  if (r0 < r1) load(r0);
+  for (int r = r0; r < r1; r += GB_R) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int c = scol + 16 * u;
+      if (c < nc) {
+        const float x = pre[u];
+        const unsigned short h0 = bf16_bits_rn(x);
+        const float x1 = x - bf16_to_float(h0);
+        const unsigned short h1 = bf16_bits_rn(x1);
+        const unsigned short h2 = bf16_bits_rn(x1 - bf16_to_float(h1));
+        const int o = c * GB_PITCH + srow;
+        sm[o] = h0;
+        sm[plane + o] = h1;
+        sm[2 * plane + o] = h2;
+      }
+    }
+    __syncthreads();
+    if (r + GB_R < r1) load(r + GB_R);
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+      if (!bv[t]) continue;
+      const int ca = (bp[t] * 16 + (lane & 15)) * GB_PITCH + koff;
+      const int cb = (toff + bq[t] * 16 + (lane & 15)) * GB_PITCH + koff;
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sm + ca);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sm + plane + ca);
+      const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(sm + 2 * plane + ca);
+      const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(sm + cb);
+      const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(sm + plane + cb);
+      const bf16x8 c2 = *reinterpret_cast<const bf16x8*>(sm + 2 * plane + cb);
+      f4v s = {0.f, 0.f, 0.f, 0.f};
+      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, c1, s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c2, s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, c0, s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c1, s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, c0, s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c0, s, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[t][q] += (double)s[q];
+    }
+  }
+  double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t) {
+    if (!bv[t]) continue;
+    const int j = bq[t] * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = bp[t] * 16 + 4 * (lane >> 4) + q;
+      if (i < ni && j < nj) out[(size_t)i * A.part_ld + j] = acc[t][q];
+    }
+  }
+}
+
 struct GramReduceArgs {
   const ElemDev* elems;
   const int* active;
@@ -1504,7 +1649,8 @@ void init_kernel_attributes() {
   static const bool done = [] {
 #define DG_GRAM_ATTR(MB)                                    \
   set_lds_limit((const void*)k_gram<double, MB>, 96000); \
-  set_lds_limit((const void*)k_gram<float, MB>, 96000);
+  set_lds_limit((const void*)k_gram_bf16<MB, 18>, 144000); \
+  set_lds_limit((const void*)k_gram_bf16<MB, 36>, 144000);
     DG_GRAM_ATTR(1)
     DG_GRAM_ATTR(2)
     DG_GRAM_ATTR(3)
@@ -1563,6 +1709,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     flops += 2.0 * r * (S.nb * ke) * (T.nb * kt);
   }
   const size_t lds = (size_t)GP_R * (nc + 1) * sizeof(double) + (size_t)nc * sizeof(void*);
+  const size_t lds_bf16 = (size_t)3 * nc * GB_PITCH * 2 + (size_t)nc * sizeof(void*);
   auto launch = [&](int ns) -> int {
     ga.nsplit = ns;
     dim3 g1(groups, ns, c.n_elem);
@@ -1571,7 +1718,10 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     if (prec == DG_FP64) {                                                                 \
       hipLaunchKernelGGL((k_gram<double, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);   \
     } else {                                                                               \
-      hipLaunchKernelGGL((k_gram<float, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);    \
+      if (nc <= 288)                                                                       \
+        hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
+      else                                                                                 \
+        hipLaunchKernelGGL((k_gram_bf16<MB, 36>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
     }                                                                                      \
     break;
     switch (maxb) {
