@@ -149,7 +149,9 @@ struct Ctx {
   int gram_part_ld = 0;
   int gram_max_split = 16;
   std::map<long long, int> gram_split_table;   // autotuned row splits per Gram shape
-  bool autotune = true;                        // DG_TUNE=0 keeps the default splits
+  bool autotune = true;
+  bool orth_w = false;                         // W <- W - X (X^T W) before the projected problem
+                                               // (DG_ORTH_W=1); by default the overlap S^T S carries it                        // DG_TUNE=0 keeps the default splits
   int nl_pending_np = 0, nl_pending_kk = 0;
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable

@@ -348,6 +348,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   if (const char* ot = std::getenv("DG_RR_ORTOL")) c->rr_ortol = std::atof(ot);
   if (const char* dt = std::getenv("DG_RR_DROP")) c->rr_drop_env = std::atof(dt);
   if (const char* tu = std::getenv("DG_TUNE")) c->autotune = std::atoi(tu) != 0;
+  if (const char* ow = std::getenv("DG_ORTH_W")) c->orth_w = std::atoi(ow) != 0;
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {

@@ -141,8 +141,9 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
     int s2;
     // W = T(HX - X Theta)  (Eq. (3), step 3)
     if ((s2 = launch_teter(c, prec, B_X, B_HX, B_W, 0, active))) return s2;
-    // W <- W - X (X^T W)
-    {
+    // W <- W - X (X^T W): optional; the projected problem on [X W P] with its overlap
+    // matrix spans the same subspace, and nearly dependent columns leave the basis there
+    if (c.orth_w) {
       ColSet SX{1, {B_X, 0, 0}}, SW{1, {B_W, 0, 0}};
       if ((s2 = launch_gram(c, prec, SX, KC_K, SW, KC_K, small_code(2), active, 0))) return s2;
       RotArgs ra{};
