@@ -7,7 +7,7 @@
 // DFT.  The lines are transformed here in registers:
 //
 //  * a line of N complex points is held by a group of TL adjacent lanes
-//    (TL in {1, 2, 4}); lane t of the group holds the M = N / TL points
+//    (TL in {1, 2, 4, 8}); lane t of the group holds the M = N / TL points
 //    j = t + TL * i, i = 0..M-1;
 //  * forward: per-lane DFT_M over i (mixed radix 4/3/2, unrolled, every index
 //    a compile-time constant so the data stays in VGPRs), twiddle W_N^{t k1},
@@ -204,6 +204,7 @@ __host__ __device__ __forceinline__ void dft_reg(cplx<T> (&x)[M]) {
 template <int TL>
 __host__ __device__ constexpr int bitrev_lane(int t) {
   if constexpr (TL == 4) return ((t & 1) << 1) | ((t >> 1) & 1);
+  else if constexpr (TL == 8) return ((t & 1) << 2) | (t & 2) | ((t >> 2) & 1);
   else return t;
 }
 
@@ -234,6 +235,17 @@ struct LineFFT {
           constexpr T r1 = Tw<T, N, DIR>::re(kk), i1 = Tw<T, N, DIR>::im(kk);
           wr = t ? r1 : T(1);
           wi = t ? i1 : T(0);
+        } else if constexpr (TL == 8) {
+          // W_N^{t k} for the lane's t in 0..7 (compile-time values, runtime select)
+          wr = T(1);
+          wi = T(0);
+          sfor<1, 8>([&](auto j) {
+            constexpr T rj = Tw<T, N, DIR>::re(CV(j) * kk), ij = Tw<T, N, DIR>::im(CV(j) * kk);
+            if (t == CV(j)) {
+              wr = rj;
+              wi = ij;
+            }
+          });
         } else {
           constexpr T r1 = Tw<T, N, DIR>::re(kk), i1 = Tw<T, N, DIR>::im(kk);
           constexpr T r2 = Tw<T, N, DIR>::re(2 * kk), i2 = Tw<T, N, DIR>::im(2 * kk);
@@ -254,10 +266,37 @@ struct LineFFT {
     });
   }
 
+  // v *= W_8^{DIR j} on lanes whose xor-4 partner is lower (t >= 4), j = t - 4
+  __device__ static __forceinline__ void w8_upper(cplx<T> (&v)[M], int t, int dir) {
+    if (t < 4) return;
+    const int j = t - 4;
+    // W_8^{dir j}: 1, (1 + dir i)/sqrt2, dir i, (-1 + dir i)/sqrt2
+    const T h = T(0.70710678118654752440);
+    const T wr = j == 0 ? T(1) : j == 1 ? h : j == 2 ? T(0) : -h;
+    const T wi = T(dir) * (j == 0 ? T(0) : j == 1 ? h : j == 2 ? T(1) : h);
+    sfor<0, M>([&](auto k) { v[CV(k)] = cmul(v[CV(k)], wr, wi); });
+  }
+
   template <int DIR>
   __device__ static __forceinline__ void cross_lane(cplx<T> (&v)[M], int t) {
     if constexpr (TL == 2) {
       xbfly(v, 1, t & 1);
+    } else if constexpr (TL == 8) {
+      // radix-2 network over the three lane bits (decimation in frequency forward,
+      // its transpose with conjugate twiddles inverse); lane t holds index bitrev(t)
+      if constexpr (DIR < 0) {
+        xbfly(v, 4, t & 4);
+        w8_upper(v, t, -1);
+        xbfly(v, 2, t & 2);
+        if ((t & 3) == 3) sfor<0, M>([&](auto k) { v[CV(k)] = cmul_i<-1>(v[CV(k)]); });
+        xbfly(v, 1, t & 1);
+      } else {
+        xbfly(v, 1, t & 1);
+        if ((t & 3) == 3) sfor<0, M>([&](auto k) { v[CV(k)] = cmul_i<+1>(v[CV(k)]); });
+        xbfly(v, 2, t & 2);
+        w8_upper(v, t, +1);
+        xbfly(v, 4, t & 4);
+      }
     } else if constexpr (TL == 4) {
       if constexpr (DIR < 0) {
         xbfly(v, 2, t & 2);

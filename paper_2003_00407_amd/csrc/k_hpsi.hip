@@ -63,7 +63,7 @@ __device__ __forceinline__ PairCols<T> pair_cols(const ElemDev& E, int blk, int 
 // plane pass: x-lines and y-lines of one z-plane, several planes per block
 // ---------------------------------------------------------------------------
 template <typename T, int NX, int NY, int TL, int MODE>
-__global__ void __launch_bounds__(256) k_plane(PlaneArgs A) {
+__global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
   constexpr int NL = NX > NY ? NX : NY;
   constexpr int TPP = NL * TL;
   constexpr int PPW = (256 / TPP) > 0 ? 256 / TPP : 1;
@@ -428,37 +428,37 @@ static void z_launch(const ZArgs& a, int nxy, int npairs, int nel, hipStream_t s
   hipLaunchKernelGGL((k_zcol<T, NZ, TL, MODE>), grid, dim3(256), 0, s, a);
 }
 
-template <typename T>
+// lanes per FFT line: FP64 lines of 32..64 points on 8 lanes (M = 4..8 values per
+// lane), shorter FP64 lines on 4, FP32 lines on 2
+template <typename T, int N>
 constexpr int lanes_per_line() {
-  return sizeof(T) == 8 ? 4 : 2;
+  return sizeof(T) == 8 ? (N >= 32 ? 8 : 4) : 2;
 }
 
 template <typename T, int MODE>
 static bool dispatch_plane(int nxy, const PlaneArgs& a, int nz, int npairs, int nel, hipStream_t s) {
-  constexpr int TL = lanes_per_line<T>();
   switch (nxy) {
-    case 8: plane_launch<T, 8, TL, MODE>(a, nz, npairs, nel, s); return true;
-    case 12: plane_launch<T, 12, TL, MODE>(a, nz, npairs, nel, s); return true;
-    case 16: plane_launch<T, 16, TL, MODE>(a, nz, npairs, nel, s); return true;
-    case 24: plane_launch<T, 24, TL, MODE>(a, nz, npairs, nel, s); return true;
-    case 32: plane_launch<T, 32, TL, MODE>(a, nz, npairs, nel, s); return true;
-    case 48: plane_launch<T, 48, TL, MODE>(a, nz, npairs, nel, s); return true;
-    case 64: plane_launch<T, 64, TL, MODE>(a, nz, npairs, nel, s); return true;
+    case 8: plane_launch<T, 8, lanes_per_line<T, 8>(), MODE>(a, nz, npairs, nel, s); return true;
+    case 12: plane_launch<T, 12, lanes_per_line<T, 12>(), MODE>(a, nz, npairs, nel, s); return true;
+    case 16: plane_launch<T, 16, lanes_per_line<T, 16>(), MODE>(a, nz, npairs, nel, s); return true;
+    case 24: plane_launch<T, 24, lanes_per_line<T, 24>(), MODE>(a, nz, npairs, nel, s); return true;
+    case 32: plane_launch<T, 32, lanes_per_line<T, 32>(), MODE>(a, nz, npairs, nel, s); return true;
+    case 48: plane_launch<T, 48, lanes_per_line<T, 48>(), MODE>(a, nz, npairs, nel, s); return true;
+    case 64: plane_launch<T, 64, lanes_per_line<T, 64>(), MODE>(a, nz, npairs, nel, s); return true;
     default: return false;
   }
 }
 
 template <typename T, int MODE>
 static bool dispatch_z(int nz, const ZArgs& a, int nxy, int npairs, int nel, hipStream_t s) {
-  constexpr int TL = lanes_per_line<T>();
   switch (nz) {
-    case 8: z_launch<T, 8, TL, MODE>(a, nxy, npairs, nel, s); return true;
-    case 12: z_launch<T, 12, TL, MODE>(a, nxy, npairs, nel, s); return true;
-    case 16: z_launch<T, 16, TL, MODE>(a, nxy, npairs, nel, s); return true;
-    case 24: z_launch<T, 24, TL, MODE>(a, nxy, npairs, nel, s); return true;
-    case 32: z_launch<T, 32, TL, MODE>(a, nxy, npairs, nel, s); return true;
-    case 48: z_launch<T, 48, TL, MODE>(a, nxy, npairs, nel, s); return true;
-    case 64: z_launch<T, 64, TL, MODE>(a, nxy, npairs, nel, s); return true;
+    case 8: z_launch<T, 8, lanes_per_line<T, 8>(), MODE>(a, nxy, npairs, nel, s); return true;
+    case 12: z_launch<T, 12, lanes_per_line<T, 12>(), MODE>(a, nxy, npairs, nel, s); return true;
+    case 16: z_launch<T, 16, lanes_per_line<T, 16>(), MODE>(a, nxy, npairs, nel, s); return true;
+    case 24: z_launch<T, 24, lanes_per_line<T, 24>(), MODE>(a, nxy, npairs, nel, s); return true;
+    case 32: z_launch<T, 32, lanes_per_line<T, 32>(), MODE>(a, nxy, npairs, nel, s); return true;
+    case 48: z_launch<T, 48, lanes_per_line<T, 48>(), MODE>(a, nxy, npairs, nel, s); return true;
+    case 64: z_launch<T, 64, lanes_per_line<T, 64>(), MODE>(a, nxy, npairs, nel, s); return true;
     default: return false;
   }
 }
