@@ -67,7 +67,9 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
   constexpr int NL = NX > NY ? NX : NY;
   constexpr int TPP = NL * TL;
   constexpr int PPW = (256 / TPP) > 0 ? 256 / TPP : 1;
-  constexpr int PITCH = NX + 1;
+  // LDS row pitch: with 8 lanes per line, NX + 2 (complex) makes the column reads of
+  // a 16-lane group (2 lines x 8 lanes) fall in distinct banks
+  constexpr int PITCH = NX + (TL == 8 ? 2 : 1);
   constexpr int MX = NX / TL, MY = NY / TL;
   using FX = LineFFT<T, NX, TL>;
   using FY = LineFFT<T, NY, TL>;
