@@ -159,7 +159,7 @@ struct Ctx {
   double rr_drop_tol = 1e-8;       // W/P columns with smaller scaled overlap pivots leave the basis
   double rr_drop_env = -1.0;       // DG_RR_DROP override (diagnostics)
   double rr_ortol = 1e-5;          // cluster tolerance of the inverse iteration (relative to ||T||)
-  long long* dev_phase = nullptr;  // diagnostics: RR phase timestamps (8 per element)
+  long long* dev_phase = nullptr;  // diagnostics: RR phase timestamps (16 per element)
 };
 
 // RAII: records a HIP event pair around the launches of one kernel class

@@ -430,6 +430,43 @@ __device__ double block_max(double v, double* sh) {
   return s;
 }
 
+// Eigenvalues 0..nwant-1 (ascending) of the symmetric tridiagonal T (diagonal sd,
+// off-diagonal se) by multisection on Sturm counts: a group of 8 lanes owns one
+// eigenvalue and counts at the 8 interior points of its bracket, which shrinks
+// 9-fold per round; the round's bracket is read off the group's ballot. The
+// bracket keeps count(lo) <= j < count(hi) and stops below abstol or a few ulps of
+// its end points. Each lane of a group computes the same bracket, so the group
+// stays converged together. Ends with a barrier.
+__device__ void multisect_eigs(const double* sd, const double* se, int m, int nwant, double lo0, double hi0,
+                               double pivmin, double abstol, double* lam) {
+  const int lane = threadIdx.x & 63;
+  const int t = lane & 7, gsh = lane & 56;
+  const int per_pass = blockDim.x >> 3;
+  for (int j0 = 0; j0 < nwant; j0 += per_pass) {
+    const int j = j0 + (threadIdx.x >> 3);
+    if (j < nwant) {
+      double lo = lo0, hi = hi0;
+      for (int r = 0; r < 80; ++r) {
+        const double w = hi - lo;
+        if (!(w > fmax(abstol, 4.0 * 2.2204460492503131e-16 * fmax(fabs(lo), fabs(hi))))) break;
+        const double step = w * (1.0 / 9.0);
+        const int cnt = sturm_count(sd, se, m, lo + step * (double)(t + 1), pivmin);
+        const unsigned bits = (unsigned)(__ballot(cnt > j) >> gsh) & 0xFFu;
+        if (bits == 0) {
+          lo = lo + step * 8.0;
+        } else {
+          const int f = __ffs(bits) - 1;   // first point whose count exceeds j
+          const double nlo = f > 0 ? lo + step * (double)f : lo;
+          hi = lo + step * (double)(f + 1);
+          lo = nlo;
+        }
+      }
+      if (t == 0) lam[j] = 0.5 * (lo + hi);
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz / symmetric eigen, one workgroup per element (FP64)
 // ---------------------------------------------------------------------------
@@ -440,424 +477,33 @@ struct RRArgs {
   int kfix;            // RR_SVD: matrix order
   int nkeep;           // columns of C to produce (<= 0: E.K)
   int mode;
-  int max_sweeps;
-  int* status;         // per element: 0 ok, 1 breakdown
-  int lds_order;       // > 0: the Jacobi matrix lives in dynamic LDS when np <= lds_order
-  long long* phase_clk;  // optional: 8 timestamps per element (diagnostics)
-  double* work;          // per element work region (inverse iteration)
+  int* status;         // per element: 0 ok, 2 breakdown of the X block
+  long long* phase_clk;  // optional: 16 timestamps per element (diagnostics)
+  double* work;          // per element work region (the working matrix above kRRLdsOrder)
   long long work_stride;
   double pivot_tol;      // X-column overlap pivots below this (after unit-diagonal scaling) = breakdown
   double drop_tol;       // W/P columns whose scaled pivot is below this are left out of the basis
   double* minpiv;        // optional: smallest scaled pivot, its column, dropped count (diagnostics)
   double ortol;          // eigenvalues closer than ortol * ||T|| are treated as one cluster
-  int lds_dyn;           // k_rr_lds: dynamic LDS bytes of the launch
+  int lds_dyn;           // dynamic LDS bytes of the launch (LDS variant)
 };
 
 constexpr int kRRThreads = 512;
 constexpr int kTriMax = 272;   // largest projected problem handled (3 x 88 + pad)
 
-__global__ void __launch_bounds__(kRRThreads) k_rr(RRArgs A) {
-  const int e = blockIdx.x;
-  const ElemDev& E = A.elems[e];
-  if (A.active && !A.active[e]) return;
-  const int K = E.K;
-  const int n = (A.mode == RR_GEN) ? A.nb * K : kcode(A.kfix, E);
-  const int np = n + (n & 1);             // padded even order for the pairing
-  const int nkeep = kcode(A.nkeep, E);
-  const int KP = E.kmax3 + 2;             // storage order of the work matrices
-  double* G = E.small + SmallLayout::G(KP);     // Gram / U / Z (KP x KP)
-  double* Am = E.small + SmallLayout::A(KP);    // A, then the standard problem
-  double* Um = E.small + SmallLayout::U(KP);
-  double* Vm = E.small + SmallLayout::V(KP);
-  double* Cm = E.small + SmallLayout::C(KP);
-  double* vec = E.small + SmallLayout::vec(KP);
-  double* d = vec + VS_D * KP;
-  __shared__ double sh[16];
-  __shared__ int brk;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  auto stamp = [&](int k) {
-    if (A.phase_clk && tid == 0) A.phase_clk[e * 8 + k] = wall_clock64();
-  };
-  stamp(0);
-  // Inputs: G and A (n x n, ld n) as written by the Gram reduction.  For the
-  // generalised problem the overlap Cholesky runs over the columns of
-  // S = [X W P] in order; a W or P column whose remaining (scaled) pivot is
-  // below drop_tol is numerically in the span of the columns before it and is
-  // left out of the basis (its coefficients are zero), which keeps the
-  // projected problem well conditioned. A breakdown inside X itself keeps X.
-  int n_cur = n;
-  int n_dropped = 0;
-  if (A.mode == RR_GEN) {
-    int attempt = 0;
-    for (;;) {
-      const int m = n_cur;
-      if (tid == 0) brk = 0;
-      __syncthreads();
-      for (int idx = tid; idx < np * np; idx += nt) {
-        const int i = idx / np, j = idx % np;
-        const bool in = (i < m && j < m);
-        Um[idx] = in ? G[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
-        Vm[idx] = in ? 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]) : 0.0;
-      }
-      __syncthreads();
-      for (int i = tid; i < np; i += nt) {
-        const double gii = Um[(size_t)i * np + i];
-        if (!(gii > 0.0) && i < K) brk = 1;
-        d[i] = (i < m && gii > 0.0) ? 1.0 / sqrt(gii) : (i < m ? 0.0 : 1.0);
-      }
-      __syncthreads();
-      for (int idx = tid; idx < np * np; idx += nt) {
-        const int i = idx / np, j = idx % np;
-        Um[idx] *= d[i] * d[j];
-        Vm[idx] *= d[i] * d[j];
-      }
-      __syncthreads();
-      // Cholesky (upper, in place in Um): Um = U^T U
-      double pmin = 1.0;
-      int jmin = -1, ndrop = 0;
-      for (int j = 0; j < m; ++j) {
-        const double piv = Um[(size_t)j * np + j];
-        if (piv < pmin) {
-          pmin = piv;
-          jmin = j;
-        }
-        if (A.mode == RR_GEN && j >= K && !(piv > A.drop_tol)) {
-          // leave column j out: unit row and column in U, zero row and column in A
-          __syncthreads();
-          for (int i = tid; i < np; i += nt) {
-            if (i == j) continue;
-            Um[(size_t)i * np + j] = 0.0;
-            Um[(size_t)j * np + i] = 0.0;
-            Vm[(size_t)i * np + j] = 0.0;
-            Vm[(size_t)j * np + i] = 0.0;
-          }
-          if (tid == 0) {
-            Um[(size_t)j * np + j] = 1.0;
-            Vm[(size_t)j * np + j] = 0.0;
-            d[j] = 0.0;
-          }
-          ++ndrop;
-          __syncthreads();
-          continue;
-        }
-        if (!(piv > A.pivot_tol) && tid == 0) brk = 1;
-        const double ujj = sqrt(fmax(piv, 1e-300));
-        __syncthreads();
-        for (int k = j + 1 + tid; k < m; k += nt) Um[(size_t)j * np + k] /= ujj;
-        __syncthreads();
-        if (tid == 0) Um[(size_t)j * np + j] = ujj;
-        const int mm = m - j - 1;
-        for (int idx = tid; idx < mm * mm; idx += nt) {
-          const int i = j + 1 + idx / mm, k = j + 1 + idx % mm;
-          if (k >= i) Um[(size_t)i * np + k] -= Um[(size_t)j * np + i] * Um[(size_t)j * np + k];
-        }
-        __syncthreads();
-      }
-      if (A.minpiv && tid == 0 && attempt == 0) {
-        A.minpiv[3 * e] = pmin;
-        A.minpiv[3 * e + 1] = jmin;
-        A.minpiv[3 * e + 2] = ndrop;
-      }
-      n_dropped = ndrop;
-      if (!brk) break;
-      ++attempt;
-      {
-        // unrecoverable: keep X (C = [I; 0; 0]) and report the status
-        for (int idx = tid; idx < n * nkeep; idx += nt) {
-          const int i = idx / nkeep, j = idx % nkeep;
-          Cm[idx] = (i == j) ? 1.0 : 0.0;
-        }
-        if (tid == 0) A.status[e] = 2;
-        return;
-      }
-      __syncthreads();
-    }
-    if (tid == 0) A.status[e] = attempt;
-    stamp(1);
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      if (j < i) Um[idx] = 0.0;
-    }
-    __syncthreads();
-    // Z = U^{-1} (upper) into G, one row per step from the bottom (rows below are final)
-    for (int idx = tid; idx < np * np; idx += nt) G[idx] = 0.0;
-    __syncthreads();
-    for (int i = n_cur - 1; i >= 0; --i) {
-      const double uii = Um[(size_t)i * np + i];
-      for (int j = i + tid; j < n_cur; j += nt) {
-        double sacc = (i == j) ? 1.0 : 0.0;
-        for (int k = i + 1; k <= j; ++k) sacc -= Um[(size_t)i * np + k] * G[(size_t)k * np + j];
-        G[(size_t)i * np + j] = sacc / uii;
-      }
-      __syncthreads();
-    }
-    stamp(2);
-    // Am = A' Z ; Um = Z^T Am ; Am = sym(Um)  (standard problem)
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      double sacc = 0.0;
-      if (i < n_cur && j < n_cur)
-        for (int k = 0; k <= j; ++k) sacc += Vm[(size_t)i * np + k] * G[(size_t)k * np + j];
-      Am[idx] = sacc;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      double sacc = 0.0;
-      if (i < n_cur && j < n_cur)
-        for (int k = 0; k <= i; ++k) sacc += G[(size_t)k * np + i] * Am[(size_t)k * np + j];
-      Um[idx] = sacc;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      Am[idx] = (i < n_cur && j < n_cur) ? 0.5 * (Um[idx] + Um[(size_t)j * np + i]) : 0.0;
-    }
-    if (n_dropped > 0) {
-      // left-out columns get an eigenvalue above the whole spectrum (Gershgorin bound)
-      __syncthreads();
-      double rmax = 0.0;
-      for (int i = tid; i < n_cur; i += nt) {
-        double sacc = 0.0;
-        for (int k = 0; k < n_cur; ++k) sacc += fabs(Am[(size_t)i * np + k]);
-        rmax = fmax(rmax, sacc);
-      }
-      rmax = block_max(rmax, sh);
-      for (int j = tid; j < n_cur; j += nt)
-        if (d[j] == 0.0) Am[(size_t)j * np + j] = 2.0 * rmax + 1.0;
-    }
-  } else {
-    // RR_SVD: eigen-decomposition of the Gram matrix itself
-    for (int idx = tid; idx < np * np; idx += nt) {
-      const int i = idx / np, j = idx % np;
-      Am[idx] = (i < n && j < n) ? G[(size_t)i * n + j] : 0.0;
-    }
-  }
-  __syncthreads();
-  stamp(3);
-  // ---- symmetric eigen-solve of the n_cur x n_cur matrix Am
-  const int m_eig = n_cur;
-  // work matrix in LDS when it fits
-  extern __shared__ double lds_dyn[];
-  double* Aj = Am;
-  if (np <= A.lds_order) {
-    for (int idx = tid; idx < np * np; idx += nt) lds_dyn[idx] = Am[idx];
-    Aj = lds_dyn;
-  }
-  __shared__ double sd[kTriMax], se[kTriMax], stau[kTriMax];
-  __shared__ double vs[kTriMax], ps[kTriMax], ws[kTriMax];
-  __syncthreads();
-  // (1) Householder tridiagonalisation; reflector k kept in column k below the diagonal
-  for (int kk = 0; kk < m_eig - 2; ++kk) {
-    const int m = m_eig - kk - 1;
-    double part = 0.0;
-    for (int i = tid; i < m; i += nt) {
-      const double x = Aj[(size_t)(kk + 1 + i) * np + kk];
-      part += x * x;
-    }
-    const double ss = block_sum(part, sh);
-    const double x0 = Aj[(size_t)(kk + 1) * np + kk];
-    if (tid == 0) sd[kk] = Aj[(size_t)kk * np + kk];
-    if (ss == 0.0) {
-      if (tid == 0) {
-        stau[kk] = 0.0;
-        se[kk] = 0.0;
-      }
-      __syncthreads();
-      continue;
-    }
-    const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
-    const double vv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-    const double tau = 2.0 / vv;
-    for (int i = tid; i < m; i += nt) vs[i] = (i == 0) ? x0 - alpha : Aj[(size_t)(kk + 1 + i) * np + kk];
-    if (tid == 0) {
-      stau[kk] = tau;
-      se[kk] = alpha;
-    }
-    __syncthreads();
-    for (int i = tid; i < m; i += nt) {
-      const double* row = Aj + (size_t)(kk + 1 + i) * np + kk + 1;
-      double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += row[j] * vs[j];
-      ps[i] = tau * acc;
-    }
-    __syncthreads();
-    double kp = 0.0;
-    for (int i = tid; i < m; i += nt) kp += vs[i] * ps[i];
-    const double Kc = 0.5 * tau * block_sum(kp, sh);
-    for (int i = tid; i < m; i += nt) ws[i] = ps[i] - Kc * vs[i];
-    __syncthreads();
-    for (int idx = tid; idx < m * m; idx += nt) {
-      const int i = idx / m, j = idx % m;
-      Aj[(size_t)(kk + 1 + i) * np + kk + 1 + j] -= vs[i] * ws[j] + ws[i] * vs[j];
-    }
-    for (int i = tid; i < m; i += nt) Aj[(size_t)(kk + 1 + i) * np + kk] = vs[i];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (m_eig >= 2) {
-      sd[m_eig - 2] = Aj[(size_t)(m_eig - 2) * np + m_eig - 2];
-      se[m_eig - 2] = Aj[(size_t)(m_eig - 1) * np + m_eig - 2];
-      stau[m_eig - 2] = 0.0;
-    }
-    sd[m_eig - 1] = Aj[(size_t)(m_eig - 1) * np + m_eig - 1];
-    se[m_eig - 1] = 0.0;
-  }
-  __syncthreads();
-  stamp(6);
-  // (2) eigenvalues by bisection on Sturm counts (thread j -> j-th smallest)
-  __shared__ double sb_lo, sb_hi, sb_norm;
-  if (tid == 0) {
-    double lo = 1e300, hi = -1e300, nrm = 0.0;
-    for (int i = 0; i < m_eig; ++i) {
-      const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m_eig - 1 ? fabs(se[i]) : 0.0);
-      lo = fmin(lo, sd[i] - r);
-      hi = fmax(hi, sd[i] + r);
-      nrm = fmax(nrm, fabs(sd[i]) + r);
-    }
-    sb_norm = fmax(nrm, 1e-300);
-    sb_lo = lo - 1e-12 * sb_norm - 1e-300;
-    sb_hi = hi + 1e-12 * sb_norm + 1e-300;
-  }
-  __syncthreads();
-  const double onenorm = sb_norm;
-  const double pivmin = 1e-300 + 1e-30 * onenorm * onenorm;
-  // eigen-indices wanted: the nkeep smallest (RR_GEN) or all (RR_SVD)
-  const int nwant = (A.mode == RR_GEN) ? min(nkeep, m_eig) : m_eig;
-  double* lam_s = vec + VS_FLAGS * KP;           // eigenvalues, ascending
-  for (int j = tid; j < nwant; j += nt) lam_s[j] = bisect_eig(sd, se, m_eig, j, sb_lo, sb_hi, pivmin);
-  __syncthreads();
-  // (3) eigenvectors of T by inverse iteration; clusters re-orthogonalised in order
-  __shared__ int cst[kTriMax];
-  __shared__ double shf[kTriMax];
-  __shared__ int maxrank;
-  if (tid == 0) {
-    // eigenvalues closer than ortol * ||T|| form a cluster whose vectors are
-    // computed in order, each re-orthogonalised against the earlier ones
-    const double ortol = A.ortol * onenorm, pertol = 10.0 * 2.2e-16 * onenorm;
-    int mr = 0;
-    for (int j = 0; j < nwant; ++j) {
-      cst[j] = (j > 0 && lam_s[j] - lam_s[j - 1] <= ortol) ? cst[j - 1] : j;
-      shf[j] = lam_s[j];
-      if (j > 0 && cst[j] != j && shf[j] < shf[j - 1] + pertol) shf[j] = shf[j - 1] + pertol;
-      mr = max(mr, j - cst[j]);
-    }
-    maxrank = mr;
-  }
-  __syncthreads();
-  double* Zv = Um;   // eigenvector j of T at Zv[j * np + i]
-  for (int rnd = 0; rnd <= maxrank; ++rnd) {
-    for (int j = tid; j < nwant; j += nt) {
-      if (j - cst[j] != rnd) continue;
-      // per-thread arrays, interleaved across threads so a wave's accesses coalesce
-      double* wk = A.work + (size_t)e * A.work_stride;
-      StridedD ta{wk + 0 * (size_t)np * kRRThreads + j, kRRThreads};
-      StridedD tb{wk + 1 * (size_t)np * kRRThreads + j, kRRThreads};
-      StridedD tu{wk + 2 * (size_t)np * kRRThreads + j, kRRThreads};
-      StridedD tl{wk + 3 * (size_t)np * kRRThreads + j, kRRThreads};
-      StridedD z{wk + 4 * (size_t)np * kRRThreads + j, kRRThreads};
-      StridedB pv{reinterpret_cast<unsigned char*>(wk + 5 * (size_t)np * kRRThreads) + j, kRRThreads};
-      tri_lu(sd, se, m_eig, shf[j], 2.2e-16 * onenorm, ta, tb, tu, tl, pv);
-      for (int i = 0; i < m_eig; ++i) z[i] = hash_unit(j, i);
-      for (int it = 0; it < 4; ++it) {
-        tri_solve(m_eig, ta, tb, tu, tl, pv, z);
-        for (int q = cst[j]; q < j; ++q) {
-          const double* zq = Zv + (size_t)q * np;
-          double dot = 0.0;
-          for (int i = 0; i < m_eig; ++i) dot += zq[i] * z[i];
-          for (int i = 0; i < m_eig; ++i) z[i] -= dot * zq[i];
-        }
-        double nn = 0.0;
-        for (int i = 0; i < m_eig; ++i) nn += z[i] * z[i];
-        nn = 1.0 / sqrt(nn);
-        for (int i = 0; i < m_eig; ++i) z[i] *= nn;
-      }
-      for (int i = 0; i < np; ++i) Zv[(size_t)j * np + i] = (i < m_eig) ? z[i] : 0.0;
-    }
-    __syncthreads();
-  }
-  stamp(7);
-  // in-order modified Gram-Schmidt of the eigenvectors of T (one vector at a time,
-  // the whole workgroup cooperating)
-  for (int j = 1; j < nwant; ++j) {
-    double* zj = Zv + (size_t)j * np;
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    for (int q = wv; q < j; q += nw) {
-      const double* zq = Zv + (size_t)q * np;
-      double dot = 0.0;
-      for (int i = lane; i < m_eig; i += 64) dot += zq[i] * zj[i];
-      dot = wave_sum(dot);
-      if (lane == 0) ps[q] = dot;
-    }
-    __syncthreads();
-    double part = 0.0;
-    for (int i = tid; i < m_eig; i += nt) {
-      double v = zj[i];
-      for (int q = 0; q < j; ++q) v -= ps[q] * Zv[(size_t)q * np + i];
-      zj[i] = v;
-      part += v * v;
-    }
-    const double nn = 1.0 / sqrt(block_sum(part, sh));
-    for (int i = tid; i < m_eig; i += nt) zj[i] *= nn;
-    __syncthreads();
-  }
-  // (4) back-transform: z <- H_0 ... H_{m-3} z (one wave per vector, lanes over rows)
-  {
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    for (int j = wv; j < nwant; j += nw) {
-      double* z = Zv + (size_t)j * np;
-      for (int kk = m_eig - 3; kk >= 0; --kk) {
-        const double tau = stau[kk];
-        if (tau == 0.0) continue;
-        double dot = 0.0;
-        for (int i = kk + 1 + lane; i < m_eig; i += 64) dot += Aj[(size_t)i * np + kk] * z[i];
-        dot = wave_sum(dot) * tau;
-        for (int i = kk + 1 + lane; i < m_eig; i += 64) z[i] -= dot * Aj[(size_t)i * np + kk];
-      }
-    }
-  }
-  __syncthreads();
-  stamp(4);
-  double* theta = vec + VS_THETA * KP;
-  if (A.mode == RR_GEN) {
-    // C = D Z V[:, :nkeep]  (n x nkeep, ld nkeep); rows of dropped blocks are zero
-    for (int idx = tid; idx < n * nkeep; idx += nt) {
-      const int i = idx / nkeep, j = idx % nkeep;
-      if (i >= n_cur || j >= nwant) {
-        Cm[(size_t)i * nkeep + j] = 0.0;
-        continue;
-      }
-      const double* vj = Zv + (size_t)j * np;
-      double sacc = 0.0;
-      for (int k = i; k < n_cur; ++k) sacc += G[(size_t)i * np + k] * vj[k];
-      Cm[(size_t)i * nkeep + j] = d[i] * sacc;
-    }
-    for (int j = tid; j < nkeep; j += nt) theta[j] = j < nwant ? lam_s[j] : 0.0;
-    __syncthreads();
-    stamp(5);
-  } else {
-    // C = V[:, sel] / sigma with sigma = sqrt(eigenvalue), descending
-    for (int idx = tid; idx < n * nkeep; idx += nt) {
-      const int i = idx / nkeep, j = idx % nkeep;
-      const int col = m_eig - 1 - j;
-      const double sg = (col >= 0) ? sqrt(fmax(lam_s[col], 0.0)) : 0.0;
-      Cm[(size_t)i * nkeep + j] = (col >= 0 && sg > 0.0) ? Zv[(size_t)col * np + i] / sg : 0.0;
-    }
-    __syncthreads();
-    for (int j = tid; j < nkeep; j += nt) theta[j] = (m_eig - 1 - j >= 0) ? sqrt(fmax(lam_s[m_eig - 1 - j], 0.0)) : 0.0;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Rayleigh-Ritz for the generalised problem (S = [X W P]) with every working
-// matrix in LDS, for orders up to kRRLdsOrder (one workgroup per element):
+// Rayleigh-Ritz for the generalised problem (S = [X W P]), one workgroup per
+// element:
 //   scaled overlap -> Cholesky with column dropping -> in-place U^{-1} = Z
-//   -> T = A~ Z, A^ = Z^T T (row-streamed from L2) -> Householder tridiagonal
-//   -> Sturm bisection -> inverse iteration (factors in LDS, batches of
-//   vectors) -> in-order Gram-Schmidt and back-transformation in LDS
-//   -> C = D Z V.
-// The LDS region is reused phase by phase; G keeps Z, Vm the scaled A and then
-// the packed reflectors, Um the eigenvectors of T between phases.
+//   -> T = A~ Z, A^ = Z^T T (FP64 MFMA) -> Householder tridiagonal
+//   -> Sturm multisection -> inverse iteration (batches of vectors)
+//   -> in-order Gram-Schmidt and back-transformation -> C = D Z V.
+// The working region W (the matrix, then the inverse-iteration factors, then
+// the eigenvectors and reflectors) is dynamic LDS for orders up to
+// kRRLdsOrder (kLds = true) and the element's slice of the Gram partial-sum
+// area in global memory above that (kLds = false; L2-resident). G keeps Z, Vm
+// the scaled A and then the packed reflectors, Um the eigenvectors of T
+// between phases.
 // ---------------------------------------------------------------------------
 constexpr int kLdsPerCU = 163840;                 // 160 KB of LDS per compute unit
 constexpr int kRRStaticLds = 21504;               // bound on k_rr_lds's static LDS
@@ -866,6 +512,7 @@ constexpr int kRRLdsOrder = 132;                  // np * np doubles fit in kRRL
 
 __device__ __forceinline__ int refl_off(int kk, int m) { return kk * (m - 1) - kk * (kk - 1) / 2; }
 
+template <bool kLds>
 __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   const int e = blockIdx.x;
   const ElemDev& E = A.elems[e];
@@ -886,7 +533,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   double* d = vec + VS_D * KP;
   double* theta = vec + VS_THETA * KP;
   double* lam_s = vec + VS_FLAGS * KP;
-  extern __shared__ double L[];
+  extern __shared__ double rr_lds[];
+  double* const L = kLds ? rr_lds : A.work + (size_t)e * A.work_stride;
   __shared__ double sh[16];
   __shared__ int brk;
   __shared__ double sd[kTriMax], se[kTriMax], stau[kTriMax];
@@ -894,7 +542,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   auto stamp = [&](int k) {
-    if (A.phase_clk && tid == 0) A.phase_clk[e * 8 + k] = wall_clock64();
+    if (A.phase_clk && tid == 0) A.phase_clk[e * 16 + k] = wall_clock64();
   };
   stamp(0);
   if (tid == 0) brk = 0;
@@ -1012,7 +660,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       const int i = idx / nkeep, j = idx % nkeep;
       Cm[idx] = (i <= j && j < n) ? d[i] * L[i * np + j] : 0.0;
     }
-    stamp(5);
+    stamp(9);
     return;
   }
   // keep Z for the coefficients
@@ -1135,11 +783,26 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       for (int i = lane; i < mr; i += 64) ws[i] = ps[i] - Kc * vs[i];
     }
     __syncthreads();
-    for (int i = wv; i < mr; i += nw) {
-      double* row = L + (kk + 1 + i) * np + kk + 1;
-      const double vi = vs[i], wi = ws[i];
-      for (int j = lane; j < mr; j += 64) row[j] -= vi * ws[j] + wi * vs[j];
-      if (lane == 0) L[(kk + 1 + i) * np + kk] = vi;
+    {
+      // this lane's entries of v and w stay in registers across the rows
+      constexpr int NQ = ((kLds ? kRRLdsOrder : kTriMax) + 63) / 64;
+      double vj[NQ], wj[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int j = lane + 64 * q;
+        vj[q] = j < mr ? vs[j] : 0.0;
+        wj[q] = j < mr ? ws[j] : 0.0;
+      }
+      for (int i = wv; i < mr; i += nw) {
+        double* row = L + (kk + 1 + i) * np + kk + 1;
+        const double vi = vs[i], wi = ws[i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int j = lane + 64 * q;
+          if (j < mr) row[j] -= vi * wj[q] + wi * vj[q];
+        }
+        if (lane == 0) L[(kk + 1 + i) * np + kk] = vi;
+      }
     }
     __syncthreads();
   }
@@ -1158,7 +821,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     for (int i = lane; i < m - 1 - kk; i += 64) dst[i] = L[(size_t)(kk + 1 + i) * np + kk];
   }
   __syncthreads();
-  stamp(6);
+  stamp(4);
   // ---- eigenvalues by bisection on Sturm counts (thread j -> j-th smallest)
   __shared__ double sb_lo, sb_hi, sb_norm;
   if (tid == 0) {
@@ -1177,8 +840,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   const double onenorm = sb_norm;
   const double pivmin = 1e-300 + 1e-30 * onenorm * onenorm;
   const int nwant = svd ? m : min(nkeep, m);
-  for (int j = tid; j < nwant; j += nt) lam_s[j] = bisect_eig(sd, se, m, j, sb_lo, sb_hi, pivmin);
-  __syncthreads();
+  multisect_eigs(sd, se, m, nwant, sb_lo, sb_hi, pivmin, 2.0 * 2.2204460492503131e-16 * onenorm, lam_s);
+  stamp(5);
   // ---- eigenvectors of T by inverse iteration, factors in LDS, R vectors per batch;
   // eigenvalues closer than ortol ||T|| form a cluster whose vectors are computed in
   // order, each re-orthogonalised against the earlier ones (read back from Um)
@@ -1198,19 +861,23 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   }
   __syncthreads();
   double* Zv = Um;   // eigenvector j of T at Zv[j * np + i]
-  const int R = min(nt, A.lds_dyn / (np * (5 * (int)sizeof(double) + 1)));
-  // vector slot of this thread: slots spread over the waves (latency hiding)
+  // R vectors per batch, each with five FP64 arrays and a byte array of length np
+  const long long wbytes = kLds ? (long long)A.lds_dyn : A.work_stride * (long long)sizeof(double);
+  const int R = (int)min((long long)nt, wbytes / (np * (5 * (int)sizeof(double) + 1)));
+  // vector of this thread: spread over the waves (latency hiding); its storage
+  // column: consecutive lanes adjacent when the whole block has a slot
   const int slot = (lane < (R + nw - 1) / nw) ? lane * nw + wv : R;
+  const int col = R == nt ? wv * 64 + lane : slot;
   for (int cb = 0; cb < nwant; cb += R) {
     for (int rnd = 0; rnd <= maxrank; ++rnd) {
       const int j = cb + slot;
       if (slot < R && j < nwant && j - cst[j] == rnd) {
-        StridedD ta{L + 0 * (size_t)np * R + slot, R};
-        StridedD tb{L + 1 * (size_t)np * R + slot, R};
-        StridedD tu{L + 2 * (size_t)np * R + slot, R};
-        StridedD tl{L + 3 * (size_t)np * R + slot, R};
-        StridedD z{L + 4 * (size_t)np * R + slot, R};
-        StridedB pv{reinterpret_cast<unsigned char*>(L + 5 * (size_t)np * R) + slot, R};
+        StridedD ta{L + 0 * (size_t)np * R + col, R};
+        StridedD tb{L + 1 * (size_t)np * R + col, R};
+        StridedD tu{L + 2 * (size_t)np * R + col, R};
+        StridedD tl{L + 3 * (size_t)np * R + col, R};
+        StridedD z{L + 4 * (size_t)np * R + col, R};
+        StridedB pv{reinterpret_cast<unsigned char*>(L + 5 * (size_t)np * R) + col, R};
         tri_lu(sd, se, m, shf[j], 2.2e-16 * onenorm, ta, tb, tu, tl, pv);
         for (int i = 0; i < m; ++i) z[i] = hash_unit(j, i);
         // an isolated eigenvalue needs no re-orthogonalisation: two solves (growth
@@ -1236,7 +903,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       __syncthreads();
     }
   }
-  stamp(7);
+  stamp(6);
   // ---- eigenvectors and reflectors into LDS: in-order Gram-Schmidt, back-transformation
   double* zl = L;                                  // nwant x np
   double* rl = L + (size_t)nwant * np;             // packed reflectors
@@ -1267,6 +934,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     }
     __syncthreads();
   }
+  stamp(7);
   // back-transform: z <- H_0 ... H_{m-3} z (one wave per vector, lanes over rows)
   for (int j = wv; j < nwant; j += nw) {
     double* z = zl + (size_t)j * np;
@@ -1281,7 +949,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     }
   }
   __syncthreads();
-  stamp(4);
+  stamp(8);
   if (svd) {
     // C = V[:, sel] / sigma with sigma = sqrt(eigenvalue), descending
     for (int idx = tid; idx < n * nkeep; idx += nt) {
@@ -1292,7 +960,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     }
     for (int j = tid; j < nkeep; j += nt) theta[j] = (m - 1 - j >= 0) ? sqrt(fmax(lam_s[m - 1 - j], 0.0)) : 0.0;
     __syncthreads();
-    stamp(5);
+    stamp(9);
     return;
   }
   // ---- C = D Z V[:, :nkeep] (n x nkeep, ld nkeep); left-out rows are zero (d = 0)
@@ -1309,7 +977,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   }
   for (int j = tid; j < nkeep; j += nt) theta[j] = j < nwant ? lam_s[j] : 0.0;
   __syncthreads();
-  stamp(5);
+  stamp(9);
 }
 
 // ---------------------------------------------------------------------------
@@ -1658,8 +1326,7 @@ void init_kernel_attributes() {
     DG_GRAM_ATTR(6)
     DG_GRAM_ATTR(8)
 #undef DG_GRAM_ATTR
-    set_lds_limit((const void*)k_rr_lds, kRRLdsBytes);
-    set_lds_limit((const void*)k_rr, 146000);
+    set_lds_limit((const void*)k_rr_lds<true>, kRRLdsBytes);
     return true;
   }();
   (void)done;
@@ -1788,51 +1455,44 @@ int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
 }
 
 int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) {
-  // largest matrix order over the elements decides the dynamic LDS size
-  int npmax = 0;
-  for (int e = 0; e < c.n_elem; ++e) {
-    const int n = mode == RR_GEN ? nb * c.K[e] : (kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
-    npmax = std::max(npmax, n + (n & 1));
-  }
-  const size_t lds_bytes = (size_t)npmax * npmax * sizeof(double);
-  // static LDS of k_rr is ~16.5 KB; 146,000 B of dynamic LDS keeps the total under 160 KB
-  const bool use_lds = lds_bytes <= 146000;
   // algorithmic flop estimate: Cholesky + inverse (n^3/3 each), two n^3 products,
   // tridiagonalisation (4n^3/3), back-transformation and coefficients (4 n^2 k)
   double flops = 0.0;
+  int npmax = 0;
+  size_t need = 0;   // bytes of the working region: matrix, then eigenvectors + reflectors
   for (int e = 0; e < c.n_elem; ++e) {
+    const int n = mode == RR_GEN ? nb * c.K[e] : (kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
+    const int npe = n + (n & 1);
+    const int nk = nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]);
+    const int nw = mode == RR_SVD ? n : std::min(nk, n);
+    npmax = std::max(npmax, npe);
+    need = std::max({need, (size_t)(nw * npe + n * (n - 1) / 2) * sizeof(double),
+                     (size_t)npe * npe * sizeof(double), (size_t)npe * 41});
     if (active && !c.active_host.empty() && !c.active_host[e]) continue;
-    const double n = mode == RR_GEN ? (double)nb * c.K[e] : (double)(kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
-    const double k = nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]);
-    flops += (mode == RR_GEN ? 2.0 / 3.0 + 2.0 : 0.0) * n * n * n + 4.0 / 3.0 * n * n * n + 4.0 * n * n * k;
+    flops += (mode == RR_GEN ? 2.0 / 3.0 + 2.0 : 0.0) * (double)n * n * n + 4.0 / 3.0 * (double)n * n * n +
+             4.0 * (double)n * n * nk;
   }
-  // every working matrix in LDS when the orders allow it (always for Cholesky QR)
-  bool lds_gen = npmax <= kRRLdsOrder;
-  size_t lds_need = 0;
-  if (lds_gen) {
-    for (int e = 0; e < c.n_elem; ++e) {
-      const int n = mode == RR_GEN ? nb * c.K[e] : (kfix > 0 ? kfix : (kfix == 0 ? c.K[e] : c.J[e]));
-      const int npe = n + (n & 1);
-      const int nw = mode == RR_SVD ? n : std::min(nkeep > 0 ? nkeep : (nkeep == 0 ? c.K[e] : c.J[e]), n);
-      const size_t phase_d = (size_t)(nw * npe + n * (n - 1) / 2) * sizeof(double);
-      const size_t mat = (size_t)npe * npe * sizeof(double);
-      lds_need = std::max({lds_need, phase_d, mat, (size_t)npe * 41});
-    }
-    if (lds_need > (size_t)kRRLdsBytes) lds_gen = false;
-  }
-  RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, 40, c.dev_status, use_lds ? npmax : 0,
-           c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
-           c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol,
-           (int)lds_need};
-  TimedScope ts(c, TC_RR, flops);
-  if (!lds_gen && mode == RR_CHOLQR) {
-    set_error("Cholesky QR of an order above the LDS limit");
+  if (npmax > kTriMax) {
+    set_error("projected problem of order " + std::to_string(npmax) + " above the limit " +
+              std::to_string(kTriMax));
     return DG_ERR_SHAPE;
   }
-  if (lds_gen) {
-    hipLaunchKernelGGL(k_rr_lds, dim3(c.n_elem), dim3(kRRThreads), lds_need, c.stream, a);
+  // the working region lives in LDS when the orders allow it, else in the element's
+  // slice of the Gram partial-sum area (free between the Gram reduction and the rotation)
+  const bool in_lds = npmax <= kRRLdsOrder && need <= (size_t)kRRLdsBytes;
+  if (!in_lds && need > (size_t)c.gram_part_stride * sizeof(double)) {
+    set_error("Rayleigh-Ritz work region of " + std::to_string(need) + " bytes above the partial-sum slice");
+    return DG_ERR_SHAPE;
+  }
+  RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, c.dev_status,
+           c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
+           c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol,
+           in_lds ? (int)need : 0};
+  TimedScope ts(c, TC_RR, flops);
+  if (in_lds) {
+    hipLaunchKernelGGL(k_rr_lds<true>, dim3(c.n_elem), dim3(kRRThreads), need, c.stream, a);
   } else {
-    hipLaunchKernelGGL(k_rr, dim3(c.n_elem), dim3(kRRThreads), use_lds ? lds_bytes : 0, c.stream, a);
+    hipLaunchKernelGGL(k_rr_lds<false>, dim3(c.n_elem), dim3(kRRThreads), 0, c.stream, a);
   }
   DG_HIP(hipGetLastError());
   return DG_OK;

@@ -430,11 +430,12 @@ static void z_launch(const ZArgs& a, int nxy, int npairs, int nel, hipStream_t s
   hipLaunchKernelGGL((k_zcol<T, NZ, TL, MODE>), grid, dim3(256), 0, s, a);
 }
 
-// lanes per FFT line: FP64 lines of 32..64 points on 8 lanes (M = 4..8 values per
-// lane), shorter FP64 lines on 4, FP32 lines on 2
+// lanes per FFT line: lines of 32..64 points on 8 lanes (M = 4..8 values per
+// lane), shorter lines on 4; the same for FP32 and FP64 (fewer values per lane keep
+// the register count, and so the occupancy, of the long-line kernels up)
 template <typename T, int N>
 constexpr int lanes_per_line() {
-  return sizeof(T) == 8 ? (N >= 32 ? 8 : 4) : 2;
+  return N >= 32 ? 8 : 4;
 }
 
 template <typename T, int MODE>

@@ -255,7 +255,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_status = take(sizeof(int) * n_elem);
   P.off_count = take(sizeof(int) * 4);
   P.off_iters = take(sizeof(int) * n_elem);
-  P.off_phase = take(sizeof(long long) * 8 * n_elem);
+  P.off_phase = take(sizeof(long long) * 16 * n_elem);
   P.off_maxres = take(sizeof(double) * n_elem);
   P.off_bounds = take(sizeof(double) * 3 * n_elem);
   P.off_de = take(sizeof(double) * n_elem);

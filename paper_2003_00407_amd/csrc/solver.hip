@@ -243,13 +243,14 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
         fprintf(stderr, "\n");
       }
       if (c.log_level >= 2 && it % 10 == 1) {
-        std::vector<long long> ph(8 * c.n_elem);
-        if ((st = sync_read(c, ph.data(), c.dev_phase, sizeof(long long) * 8 * c.n_elem))) return st;
-        fprintf(stderr, "[dg] rr phases (us): chol %.0f zinv %.0f matmul %.0f tridiag %.0f invit %.0f "
-                "mgs+back %.0f coeff %.0f\n",
-                (ph[1] - ph[0]) / 100.0, (ph[2] - ph[1]) / 100.0, (ph[3] - ph[2]) / 100.0,
-                (ph[6] - ph[3]) / 100.0, (ph[7] - ph[6]) / 100.0, (ph[4] - ph[7]) / 100.0,
-                (ph[5] - ph[4]) / 100.0);
+        std::vector<long long> ph(16 * c.n_elem);
+        if ((st = sync_read(c, ph.data(), c.dev_phase, sizeof(long long) * 16 * c.n_elem))) return st;
+        // wall clock at 100 MHz; element 0
+        static const char* names[9] = {"chol", "zinv", "matmul", "tridiag", "bisect", "invit", "mgs", "back",
+                                       "coeff"};
+        fprintf(stderr, "[dg] rr phases (us):");
+        for (int k = 0; k < 9; ++k) fprintf(stderr, " %s %.0f", names[k], (ph[k + 1] - ph[k]) / 100.0);
+        fprintf(stderr, "\n");
       }
     }
     if (cnt[0] == 0) break;
