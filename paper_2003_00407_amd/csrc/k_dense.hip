@@ -1094,6 +1094,152 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
 }
 
 // ---------------------------------------------------------------------------
+// The same rotation for FP32 blocks on BF16 matrix cores (the FP32 stage of the
+// mixed path): S values and C coefficients are split into three BF16 pieces each
+// (24 significant bits), and the six products s_a c_b with a + b <= 2 of every
+// 32-row step of C go to v_mfma_f32_16x16x32_bf16, smallest first, summed in FP32.
+// out^T = C^T S^T as in k_rotate: the A operand is a 16-column tile of C^T (staged
+// as three BF16 planes in LDS, the 32 C rows of a step contiguous per column), the
+// B operand 32 S columns of 16 grid rows (eight per lane, split in registers).
+// ---------------------------------------------------------------------------
+constexpr int RB_K = 32;        // C rows per MFMA step
+constexpr int RB_PITCH = 40;    // BF16 per staged C column (32 rows + pad)
+
+typedef unsigned short us8v __attribute__((ext_vector_type(8)));
+
+template <int NCT>
+__global__ void __launch_bounds__(RT_THREADS, 2) k_rotate_bf16(RotArgs A) {
+  const int e = blockIdx.y;
+  const ElemDev& E = A.elems[e];
+  if (A.active && !A.active[e]) return;
+  const int kS = kcode(A.kS, E);
+  const int ncol = kcode(A.ncol, E);
+  const int cld = A.c_ld > 0 ? A.c_ld : ncol;
+  const int nrows = nrows_of(E, A.rows_e);
+  const int r0 = blockIdx.x * RT_ROWS;
+  if (r0 >= nrows) return;
+  int c0[2], c1[2];
+  for (int o = 0; o < 2; ++o) {
+    c0[o] = A.c_blockrows > 0 ? A.c0[o] * kS : A.c0[o];
+    c1[o] = A.c_blockrows > 0 ? A.c1[o] * kS : A.c1[o];
+  }
+  __shared__ __attribute__((aligned(16))) unsigned short scb[3][NCT * 16][RB_PITCH];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kl = lane >> 4;
+  int rrow[RT_RT];
+#pragma unroll
+  for (int u = 0; u < RT_RT; ++u) rrow[u] = r0 + (w * RT_RT + u) * 16 + (lane & 15);
+  const int nct = (ncol + 15) / 16;
+  const double* Cm = E.small + soff(A.c_off, E);
+  f4v acc[RT_RT][NCT];
+#pragma unroll
+  for (int u = 0; u < RT_RT; ++u)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[u][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int nseg = A.nout > 1 ? 2 : 1;
+  for (int sg = 0; sg < nseg; ++sg) {
+    int lo, hi;
+    if (A.nout > 1) {
+      lo = sg == 0 ? c0[1] : c0[0];
+      hi = sg == 0 ? c1[1] : c0[1];
+    } else {
+      lo = c0[0];
+      hi = c1[0];
+    }
+    // S values of the next step (columns cb + 8 kl + i, rows rrow[u]) are loaded
+    // while the current step is multiplied
+    float sv[RT_RT][8], sn[RT_RT][8];
+    auto load_s = [&](int cb, float (&dst)[RT_RT][8]) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int c = cb + 8 * kl + i;
+        const float* col = c < hi ? vcol<float>(E, A.S, c, kS) : nullptr;
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) dst[u][i] = (col && rrow[u] < nrows) ? col[rrow[u]] : 0.f;
+      }
+    };
+    if (lo < hi) load_s(lo, sn);
+    for (int cb = lo; cb < hi; cb += RB_K) {
+      __syncthreads();
+      // C rows cb .. cb+31 as three BF16 planes, transposed (scb[piece][column j][row k])
+      for (int idx = threadIdx.x; idx < RB_K * NCT * 16; idx += RT_THREADS) {
+        const int j = idx % (NCT * 16), k = idx / (NCT * 16);
+        const int c = cb + k;
+        const double v = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        const unsigned short h0 = bf16_bits_rn((float)v);
+        const double v1 = v - (double)bf16_to_float(h0);
+        const unsigned short h1 = bf16_bits_rn((float)v1);
+        const unsigned short h2 = bf16_bits_rn((float)(v1 - (double)bf16_to_float(h1)));
+        scb[0][j][k] = h0;
+        scb[1][j][k] = h1;
+        scb[2][j][k] = h2;
+      }
+#pragma unroll
+      for (int u = 0; u < RT_RT; ++u)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sv[u][i] = sn[u][i];
+      __syncthreads();
+      if (cb + RB_K < hi) load_s(cb + RB_K, sn);
+      bf16x8 b0[RT_RT], b1[RT_RT], b2[RT_RT];
+#pragma unroll
+      for (int u = 0; u < RT_RT; ++u) {
+        us8v p0, p1, p2;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float x = sv[u][i];
+          const unsigned short h0 = bf16_bits_rn(x);
+          const float x1 = x - bf16_to_float(h0);
+          const unsigned short h1 = bf16_bits_rn(x1);
+          p0[i] = h0;
+          p1[i] = h1;
+          p2[i] = bf16_bits_rn(x1 - bf16_to_float(h1));
+        }
+        b0[u] = __builtin_bit_cast(bf16x8, p0);
+        b1[u] = __builtin_bit_cast(bf16x8, p1);
+        b2[u] = __builtin_bit_cast(bf16x8, p2);
+      }
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        if (t >= nct) continue;
+        const int j = t * 16 + (lane & 15);
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&scb[0][j][8 * kl]);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&scb[1][j][8 * kl]);
+        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&scb[2][j][8 * kl]);
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) {
+          f4v s = acc[u][t];
+          s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0[u], s, 0, 0, 0);
+          s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[u], s, 0, 0, 0);
+          s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2[u], s, 0, 0, 0);
+          s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0[u], s, 0, 0, 0);
+          s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1[u], s, 0, 0, 0);
+          acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[u], s, 0, 0, 0);
+        }
+      }
+    }
+    // store the output this segment completes: lane holds out[row rrow[u]][col 16 t + 4 kl + q]
+    const int o = (A.nout > 1 && sg == 0) ? 1 : 0;
+    float* out = reinterpret_cast<float*>(E.blk[A.out_blk[o]]);
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      if (t >= nct) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = t * 16 + 4 * kl + q;
+        if (j >= ncol) continue;
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) {
+          if (rrow[u] >= nrows) continue;
+          float* p = out + (size_t)j * E.ld + rrow[u];
+          const double prev = A.beta[o] != 0.0 ? A.beta[o] * (double)*p : 0.0;
+          *p = (float)(prev + A.alpha * (double)acc[u][t][q]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // residual norms and preconditioner energies
 // res_i = ||hx_i - theta_i x_i||,  ekin_i = max(theta_i - x_i^T V x_i, 0.05)
 // ---------------------------------------------------------------------------
@@ -1517,13 +1663,13 @@ int launch_rotate(Ctx& c, int prec, const RotArgs& a_in) {
     }
   }
   TimedScope ts(c, TC_ROT, flops);
-  // output column tiles: 3 (up to 48 columns) or 6 (up to 96)
+  // output column tiles: 3 (up to 48 columns) or 6 (up to 96); FP32 blocks on BF16 matrix cores
   if (k <= 48) {
     if (prec == DG_FP64) hipLaunchKernelGGL((k_rotate<double, 3>), g, dim3(RT_THREADS), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_rotate<float, 3>), g, dim3(RT_THREADS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rotate_bf16<3>), g, dim3(RT_THREADS), 0, c.stream, a);
   } else {
     if (prec == DG_FP64) hipLaunchKernelGGL((k_rotate<double, 6>), g, dim3(RT_THREADS), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_rotate<float, 6>), g, dim3(RT_THREADS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rotate_bf16<6>), g, dim3(RT_THREADS), 0, c.stream, a);
   }
   DG_HIP(hipGetLastError());
   return DG_OK;
