@@ -636,24 +636,54 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   }
   if (tid == 0) A.status[e] = 0;
   stamp(1);
-  // ---- Z = U^{-1} in place, column by column (column j uses the inverted leading block):
-  // Z[i][j] = -(1/U[j][j]) sum_{k=i}^{j-1} Z[i][k] U[k][j]
-  for (int j = 0; j < n; ++j) {
-    for (int k = tid; k < j; k += nt) vs[k] = L[k * np + j];
+  if constexpr (kLds) {
+    // ---- Z = U^{-1}: rows are independent, Z[i][j] = -(1/U[j][j]) sum_{k=i}^{j-1} Z[i][k] U[k][j]
+    // left to right. A quad of lanes owns a row (the k sum split four ways, DPP quad
+    // reduction); Z[i][j] is kept transposed in the free strictly lower triangle
+    // (L[j][i]), the reciprocal diagonal in ws, so U stays intact until every row is
+    // done; then Z moves to the upper triangle.
+    for (int i = tid; i < n; i += nt) ws[i] = 1.0 / L[i * np + i];
     __syncthreads();
-    const double ajj = 1.0 / L[j * np + j];
-    for (int i = wv; i < j; i += nw) {
-      const double* zi = L + i * np;
-      double t = 0.0;
-      for (int k = i + lane; k < j; k += 64) t += zi[k] * vs[k];
-      t = wave_sum_dpp(t);
-      if (lane == 0) ps[i] = -ajj * t;
+    {
+      const int ql = tid & 3;
+      for (int i = tid >> 2; i < n; i += nt >> 2) {
+        const double zii = ws[i];
+        for (int j = i + 1; j < n; ++j) {
+          double t = 0.0;
+          for (int k = i + ql; k < j; k += 4) t += (k == i ? zii : L[k * np + i]) * L[k * np + j];
+          t += dpp_mov<0xB1>(t);   // quad_perm [1,0,3,2]
+          t += dpp_mov<0x4E>(t);   // quad_perm [2,3,0,1]
+          if (ql == 0) L[j * np + i] = -ws[j] * t;
+        }
+      }
     }
     __syncthreads();
-    for (int i = tid; i < j; i += nt) L[i * np + j] = ps[i];
-    if (tid == 0) L[j * np + j] = ajj;
+    for (int idx = tid; idx < n * n; idx += nt) {
+      const int i = idx / n, j = idx % n;
+      if (i < j) L[i * np + j] = L[j * np + i];
+      else if (i == j) L[i * np + i] = ws[i];
+    }
+    __syncthreads();
+  } else {
+    // ---- Z = U^{-1} in place, column by column (column j uses the inverted leading block):
+    // Z[i][j] = -(1/U[j][j]) sum_{k=i}^{j-1} Z[i][k] U[k][j]
+    for (int j = 0; j < n; ++j) {
+      for (int k = tid; k < j; k += nt) vs[k] = L[k * np + j];
+      __syncthreads();
+      const double ajj = 1.0 / L[j * np + j];
+      for (int i = wv; i < j; i += nw) {
+        const double* zi = L + i * np;
+        double t = 0.0;
+        for (int k = i + lane; k < j; k += 64) t += zi[k] * vs[k];
+        t = wave_sum_dpp(t);
+        if (lane == 0) ps[i] = -ajj * t;
+      }
+      __syncthreads();
+      for (int i = tid; i < j; i += nt) L[i * np + j] = ps[i];
+      if (tid == 0) L[j * np + j] = ajj;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (!gen) {
     // Cholesky QR: C = D Z orthonormalises the columns (n x nkeep)
     for (int idx = tid; idx < n * nkeep; idx += nt) {
