@@ -1076,20 +1076,49 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
         for (int u = 0; u < RT_RT; ++u) dst[ks][u] = (col && rrow[u] < nrows) ? double(col[rrow[u]]) : 0.0;
       }
     };
-    if (lo < hi) load_s(lo, an);
-    for (int cb = lo; cb < hi; cb += RT_CC) {
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < RT_CC * NCT * 16; idx += RT_THREADS) {
+    // with six column tiles (two waves per SIMD, registers to spare) the C rows of the
+    // next chunk are prefetched into registers as well; with three (four waves per
+    // SIMD) they are read when staged
+    constexpr bool kPrefC = NCT > 3;
+    constexpr int CPT = kPrefC ? (RT_CC * NCT * 16 + RT_THREADS - 1) / RT_THREADS : 1;
+    double cn[CPT];
+    auto load_c = [&](int cb) {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int idx = threadIdx.x + u * RT_THREADS;
         const int cc = idx / (NCT * 16), j = idx % (NCT * 16);
         const int c = cb + cc;
-        sc[cc][j] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        cn[u] = (idx < RT_CC * NCT * 16 && c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+      }
+    };
+    if (lo < hi) {
+      load_s(lo, an);
+      if constexpr (kPrefC) load_c(lo);
+    }
+    for (int cb = lo; cb < hi; cb += RT_CC) {
+      __syncthreads();
+      if constexpr (kPrefC) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+          const int idx = threadIdx.x + u * RT_THREADS;
+          if (idx < RT_CC * NCT * 16) sc[idx / (NCT * 16)][idx % (NCT * 16)] = cn[u];
+        }
+      } else {
+        for (int idx = threadIdx.x; idx < RT_CC * NCT * 16; idx += RT_THREADS) {
+          const int cc = idx / (NCT * 16), j = idx % (NCT * 16);
+          const int c = cb + cc;
+          sc[cc][j] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        }
       }
 #pragma unroll
       for (int ks = 0; ks < RT_CC / 4; ++ks)
 #pragma unroll
         for (int u = 0; u < RT_RT; ++u) av[ks][u] = an[ks][u];
       __syncthreads();
-      if (cb + RT_CC < hi) load_s(cb + RT_CC, an);
+      if (cb + RT_CC < hi) {
+        load_s(cb + RT_CC, an);
+        if constexpr (kPrefC) load_c(cb + RT_CC);
+      }
 #pragma unroll
       for (int ks = 0; ks < RT_CC / 4; ++ks) {
 #pragma unroll
@@ -1188,14 +1217,39 @@ __global__ void __launch_bounds__(RT_THREADS, 2) k_rotate_bf16(RotArgs A) {
         for (int u = 0; u < RT_RT; ++u) dst[u][i] = (col && rrow[u] < nrows) ? col[rrow[u]] : 0.f;
       }
     };
-    if (lo < hi) load_s(lo, sn);
+    // with six column tiles the C rows of the next step are prefetched into registers
+    // too; with three they are read when staged (the registers would cost occupancy)
+    constexpr bool kPrefC = NCT > 3;
+    constexpr int CPT = (RB_K * NCT * 16 + RT_THREADS - 1) / RT_THREADS;
+    double cn[kPrefC ? CPT : 1];
+    auto load_c = [&](int cb) {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int idx = threadIdx.x + u * RT_THREADS;
+        const int j = idx % (NCT * 16), k = idx / (NCT * 16);
+        const int c = cb + k;
+        if constexpr (kPrefC) cn[u] = (idx < RB_K * NCT * 16 && c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+      }
+    };
+    if (lo < hi) {
+      load_s(lo, sn);
+      if constexpr (kPrefC) load_c(lo);
+    }
     for (int cb = lo; cb < hi; cb += RB_K) {
       __syncthreads();
       // C rows cb .. cb+31 as three BF16 planes, transposed (scb[piece][column j][row k])
-      for (int idx = threadIdx.x; idx < RB_K * NCT * 16; idx += RT_THREADS) {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int idx = threadIdx.x + u * RT_THREADS;
+        if (idx >= RB_K * NCT * 16) continue;
         const int j = idx % (NCT * 16), k = idx / (NCT * 16);
-        const int c = cb + k;
-        const double v = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        double v;
+        if constexpr (kPrefC) {
+          v = cn[u];
+        } else {
+          const int c = cb + k;
+          v = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        }
         const unsigned short h0 = bf16_bits_rn((float)v);
         const double v1 = v - (double)bf16_to_float(h0);
         const unsigned short h1 = bf16_bits_rn((float)v1);
@@ -1209,7 +1263,10 @@ __global__ void __launch_bounds__(RT_THREADS, 2) k_rotate_bf16(RotArgs A) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) sv[u][i] = sn[u][i];
       __syncthreads();
-      if (cb + RB_K < hi) load_s(cb + RB_K, sn);
+      if (cb + RB_K < hi) {
+        load_s(cb + RB_K, sn);
+        if constexpr (kPrefC) load_c(cb + RB_K);
+      }
       bf16x8 b0[RT_RT], b1[RT_RT], b2[RT_RT];
 #pragma unroll
       for (int u = 0; u < RT_RT; ++u) {
