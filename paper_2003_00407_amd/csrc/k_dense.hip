@@ -951,31 +951,70 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
       if (lane == 0) ps[q] = dot;
     }
     __syncthreads();
-    if (wv == 0) {
+    // z_j -= sum_q (z_q . z_j) z_q: a quad of lanes per row, the q sum split four ways;
+    // per-wave sums of squares for the norm
+    {
+      const int ql = tid & 3;
       double part = 0.0;
-      for (int i = lane; i < m; i += 64) {
-        double v = zj[i];
-        for (int q = 0; q < j; ++q) v -= ps[q] * zl[q * np + i];
-        zj[i] = v;
-        part += v * v;
+      for (int i = tid >> 2; i < m; i += nt >> 2) {
+        double t = 0.0;
+        for (int q = ql; q < j; q += 4) t += ps[q] * zl[q * np + i];
+        t += dpp_mov<0xB1>(t);   // quad_perm [1,0,3,2]
+        t += dpp_mov<0x4E>(t);   // quad_perm [2,3,0,1]
+        if (ql == 0) {
+          const double v = zj[i] - t;
+          zj[i] = v;
+          part += v * v;
+        }
       }
-      const double nn = 1.0 / sqrt(wave_sum_dpp(part));
-      for (int i = lane; i < m; i += 64) zj[i] *= nn;
+      part = wave_sum_dpp(part);
+      if (lane == 0) sh[wv] = part;
+    }
+    __syncthreads();
+    {
+      double nn2 = 0.0;
+      for (int q = 0; q < nw; ++q) nn2 += sh[q];
+      const double nn = 1.0 / sqrt(nn2);
+      for (int i = tid; i < m; i += nt) zj[i] *= nn;
     }
     __syncthreads();
   }
   stamp(7);
-  // back-transform: z <- H_0 ... H_{m-3} z (one wave per vector, lanes over rows)
-  for (int j = wv; j < nwant; j += nw) {
-    double* z = zl + (size_t)j * np;
-    for (int kk = m - 3; kk >= 0; --kk) {
-      const double tau = stau[kk];
-      if (tau == 0.0) continue;
-      const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
-      double dot = 0.0;
-      for (int i = lane; i < m - 1 - kk; i += 64) dot += v[i] * z[kk + 1 + i];
-      dot = wave_sum_dpp(dot) * tau;
-      for (int i = lane; i < m - 1 - kk; i += 64) z[kk + 1 + i] -= dot * v[i];
+  // back-transform: z <- H_0 ... H_{m-3} z (lanes over rows); a wave carries four of
+  // its vectors through the reflectors together, so that their dot products and
+  // reductions overlap
+  {
+    constexpr int BV = 4;
+    for (int j0 = wv; j0 < nwant; j0 += BV * nw) {
+      double* z[BV];
+      bool on[BV];
+#pragma unroll
+      for (int b = 0; b < BV; ++b) {
+        const int j = j0 + b * nw;
+        on[b] = j < nwant;
+        z[b] = zl + (size_t)(on[b] ? j : j0) * np;
+      }
+      for (int kk = m - 3; kk >= 0; --kk) {
+        const double tau = stau[kk];
+        if (tau == 0.0) continue;
+        const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
+        double dot[BV];
+#pragma unroll
+        for (int b = 0; b < BV; ++b) dot[b] = 0.0;
+        for (int i = lane; i < m - 1 - kk; i += 64) {
+          const double vi = v[i];
+#pragma unroll
+          for (int b = 0; b < BV; ++b) dot[b] += vi * z[b][kk + 1 + i];
+        }
+#pragma unroll
+        for (int b = 0; b < BV; ++b) dot[b] = wave_sum_dpp(dot[b]) * tau;
+        for (int i = lane; i < m - 1 - kk; i += 64) {
+          const double vi = v[i];
+#pragma unroll
+          for (int b = 0; b < BV; ++b)
+            if (on[b]) z[b][kk + 1 + i] -= dot[b] * vi;
+        }
+      }
     }
   }
   __syncthreads();
