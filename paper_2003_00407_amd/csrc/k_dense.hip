@@ -1377,8 +1377,11 @@ struct ResArgs {
   int kp;              // small storage order (kmax3 + 2)
 };
 
+// one workgroup of RES_THREADS per column; each thread keeps four rows in flight
+constexpr int RES_THREADS = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_residual(ResArgs A) {
+__global__ void __launch_bounds__(RES_THREADS) k_residual(ResArgs A) {
   const int e = blockIdx.y;
   const ElemDev& E = A.elems[e];
   const int i = blockIdx.x;
@@ -1390,19 +1393,25 @@ __global__ void __launch_bounds__(256) k_residual(ResArgs A) {
   const double th = vec[VS_THETA * KP + i];
   const T* x = reinterpret_cast<const T*>(E.blk[A.x_blk]) + (size_t)i * E.ld;
   const T* hx = reinterpret_cast<const T*>(E.blk[A.hx_blk]) + (size_t)i * E.ld;
-  double s1 = 0.0, s2 = 0.0;
-  for (int r = threadIdx.x; r < E.N; r += blockDim.x) {
-    const double xv = double(x[r]);
-    const double rv = double(hx[r]) - th * xv;
-    s1 += rv * rv;
-    s2 += E.v64[r] * xv * xv;
+  double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = threadIdx.x; r0 < E.N; r0 += 4 * RES_THREADS) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * RES_THREADS;
+      if (r < E.N) {
+        const double xv = double(x[r]);
+        const double rv = double(hx[r]) - th * xv;
+        s1[u] += rv * rv;
+        s2[u] += E.v64[r] * xv * xv;
+      }
+    }
   }
   __shared__ double sh[16];
-  s1 = block_sum(s1, sh);
-  s2 = block_sum(s2, sh);
+  const double t1 = block_sum((s1[0] + s1[1]) + (s1[2] + s1[3]), sh);
+  const double t2 = block_sum((s2[0] + s2[1]) + (s2[2] + s2[3]), sh);
   if (threadIdx.x == 0) {
-    vec[VS_RES * KP + i] = sqrt(s1);
-    vec[VS_EKIN * KP + i] = fmax(th - s2, 0.05);
+    vec[VS_RES * KP + i] = sqrt(t1);
+    vec[VS_EKIN * KP + i] = fmax(th - t2, 0.05);
   }
 }
 
@@ -1807,8 +1816,8 @@ int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int
   ResArgs a{c.elems_dev, active, x_blk, hx_blk, ncol, 0};
   dim3 g(maxk, c.n_elem);
   TimedScope ts(c, TC_OTHER);
-  if (prec == DG_FP64) hipLaunchKernelGGL(k_residual<double>, g, dim3(256), 0, c.stream, a);
-  else hipLaunchKernelGGL(k_residual<float>, g, dim3(256), 0, c.stream, a);
+  if (prec == DG_FP64) hipLaunchKernelGGL(k_residual<double>, g, dim3(RES_THREADS), 0, c.stream, a);
+  else hipLaunchKernelGGL(k_residual<float>, g, dim3(RES_THREADS), 0, c.stream, a);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
