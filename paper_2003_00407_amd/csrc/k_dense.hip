@@ -1599,6 +1599,7 @@ void init_kernel_attributes() {
 #define DG_GRAM_ATTR(MB)                                    \
   set_lds_limit((const void*)k_gram<double, MB>, 96000); \
   set_lds_limit((const void*)k_gram_bf16<MB, 18>, 144000); \
+  set_lds_limit((const void*)k_gram_bf16<MB, 26>, 144000); \
   set_lds_limit((const void*)k_gram_bf16<MB, 36>, 144000);
     DG_GRAM_ATTR(1)
     DG_GRAM_ATTR(2)
@@ -1629,10 +1630,13 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   const int nblk = sym ? bi * (bi + 1) / 2 : bi * bj;
   // output blocks per wave: the smallest instantiated count that covers the result,
   // else 8 (larger results take several workgroups, each re-reading the columns)
+  // (FP32 data with 289..416 staged columns: at most 6, which keeps the 26 staged values
+  // per thread and the accumulators in registers)
   static const int kMaxbList[] = {1, 2, 3, 4, 6, 8};
-  int maxb = 8;
+  const int maxb_top = (prec != DG_FP64 && nc > 288 && nc <= 416) ? 6 : 8;
+  int maxb = maxb_top;
   for (int m : kMaxbList)
-    if (8 * m >= nblk) {
+    if (m <= maxb_top && 8 * m >= nblk) {
       maxb = m;
       break;
     }
@@ -1668,6 +1672,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     } else {                                                                               \
       if (nc <= 288)                                                                       \
         hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
+      else if (nc <= 416)                                                                  \
+        hipLaunchKernelGGL((k_gram_bf16<MB, 26>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
       else                                                                                 \
         hipLaunchKernelGGL((k_gram_bf16<MB, 36>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
     }                                                                                      \
