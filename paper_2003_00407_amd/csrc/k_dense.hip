@@ -1633,7 +1633,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   // (FP32 data with 289..416 staged columns: at most 6, which keeps the 26 staged values
   // per thread and the accumulators in registers)
   static const int kMaxbList[] = {1, 2, 3, 4, 6, 8};
-  const int maxb_top = (prec != DG_FP64 && nc > 288 && nc <= 416) ? 6 : 8;
+  const int maxb_top = prec == DG_FP64 || nc <= 288 ? 8 : (nc <= 416 ? 6 : 4);
   int maxb = maxb_top;
   for (int m : kMaxbList)
     if (m <= maxb_top && 8 * m >= nblk) {
