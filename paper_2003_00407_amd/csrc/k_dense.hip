@@ -1032,17 +1032,28 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     stamp(9);
     return;
   }
-  // ---- C = D Z V[:, :nkeep] (n x nkeep, ld nkeep); left-out rows are zero (d = 0)
-  for (int idx = tid; idx < n * nkeep; idx += nt) {
-    const int i = idx / nkeep, j = idx % nkeep;
-    if (j >= nwant) {
-      Cm[(size_t)i * nkeep + j] = 0.0;
-      continue;
+  // ---- C = D Z V[:, :nkeep] (n x nkeep, ld nkeep) as 16x16 FP64 MFMA tiles (one wave
+  // per tile; Z[i][k] = 0 for k < i, so a tile's k range starts at its first row);
+  // left-out rows are zero (d = 0)
+  {
+    const int nti = (n + 15) >> 4, ntj = (nkeep + 15) >> 4;
+    const int kst = (n + 3) >> 2;
+    for (int tile = wv; tile < nti * ntj; tile += nw) {
+      const int ti = tile / ntj, tj = tile % ntj;
+      const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      for (int ks = ti * 4; ks < kst; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const double av = (ia < n && k < n && k >= ia) ? G[(size_t)ia * np + k] : 0.0;
+        const double bv = (jb < nwant && k < n) ? zl[(size_t)jb * np + k] : 0.0;
+        acc = mfma16x16x4(av, bv, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ti * 16 + (lane >> 4) + 4 * q;
+        if (i < n && jb < nkeep) Cm[(size_t)i * nkeep + jb] = jb < nwant ? d[i] * acc[q] : 0.0;
+      }
     }
-    const double* vj = zl + (size_t)j * np;
-    double sacc = 0.0;
-    for (int k = i; k < n; ++k) sacc += G[(size_t)i * np + k] * vj[k];
-    Cm[(size_t)i * nkeep + j] = d[i] * sacc;
   }
   for (int j = tid; j < nkeep; j += nt) theta[j] = j < nwant ? lam_s[j] : 0.0;
   __syncthreads();
