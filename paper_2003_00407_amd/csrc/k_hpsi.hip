@@ -375,6 +375,9 @@ __global__ void __launch_bounds__(256) k_nl_overlap(NlArgs A) {
 
 // y[r, j] += sum_{p in row r} b_p(r) gamma_p C[p, j] over the active points
 constexpr int kNlApplyCols = 16;
+// LDS row pitch of the gamma C table: odd in doubles, so that lanes reading the rows
+// of different projectors fall in different banks
+constexpr int kNlApplyPitch = kNlApplyCols + 1;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_nl_apply(NlArgs A) {
@@ -385,10 +388,10 @@ __global__ void __launch_bounds__(256) k_nl_apply(NlArgs A) {
   const int c0 = blockIdx.y * kNlApplyCols;
   if (c0 >= ncols || E.nact == 0) return;
   const int nc = min(kNlApplyCols, ncols - c0);
-  extern __shared__ double gc[];   // nproj x kNlApplyCols: gamma_p C[p, c0 + j]
+  extern __shared__ double gc[];   // nproj x kNlApplyPitch: gamma_p C[p, c0 + j]
   for (int i = threadIdx.x; i < E.nproj * kNlApplyCols; i += blockDim.x) {
     const int p = i / kNlApplyCols, j = i % kNlApplyCols;
-    gc[i] = (j < nc) ? E.gamma[p] * E.nlc[(size_t)p * E.kmax3 + c0 + j] : 0.0;
+    gc[p * kNlApplyPitch + j] = (j < nc) ? E.gamma[p] * E.nlc[(size_t)p * E.kmax3 + c0 + j] : 0.0;
   }
   __syncthreads();
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -405,7 +408,7 @@ __global__ void __launch_bounds__(256) k_nl_apply(NlArgs A) {
     const int p = E.ent_proj[q];
     const double bv = double(ev[q]);
 #pragma unroll
-    for (int j = 0; j < kNlApplyCols; ++j) acc[j] += bv * gc[p * kNlApplyCols + j];
+    for (int j = 0; j < kNlApplyCols; ++j) acc[j] += bv * gc[p * kNlApplyPitch + j];
   }
   T* Y = reinterpret_cast<T*>(E.blk[A.out_blk]);
 #pragma unroll
@@ -551,7 +554,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
       if (elem < 0 || e == elem) nact = std::max(nact, c.elems_host[e].nact);
     dim3 g2((nact + 255) / 256, (c.nl_pending_kk + kNlApplyCols - 1) / kNlApplyCols,
             elem >= 0 ? 1 : c.n_elem);
-    size_t shm = (size_t)c.nl_pending_np * kNlApplyCols * sizeof(double);
+    size_t shm = (size_t)c.nl_pending_np * kNlApplyPitch * sizeof(double);
     TimedScope ts(c, TC_NL);
     hipLaunchKernelGGL(k_nl_apply<T>, g2, dim3(256), shm, s, na);
   }
