@@ -227,25 +227,34 @@ struct LineFFT {
   // v *= W_N^{DIR t k} for k = 0..M-1 (t = lane within the group, runtime)
   template <int DIR>
   __device__ static __forceinline__ void lane_twiddle(cplx<T> (&v)[M], int t) {
-    if constexpr (TL > 1) {
+    if constexpr (TL == 8) {
+      // W_N^{t k} = (W_N^t)^k: the lane's root is selected once among eight
+      // compile-time values, its powers follow by complex products (a few ulps, k < 8)
+      T r1 = T(1), i1 = T(0);
+      sfor<1, 8>([&](auto j) {
+        constexpr T rj = Tw<T, N, DIR>::re(CV(j)), ij = Tw<T, N, DIR>::im(CV(j));
+        if (t == CV(j)) {
+          r1 = rj;
+          i1 = ij;
+        }
+      });
+      T wr = r1, wi = i1;
+      sfor<1, M>([&](auto k) {
+        v[CV(k)] = cmul(v[CV(k)], wr, wi);
+        if constexpr (CV(k) + 1 < M) {
+          const T nr = wr * r1 - wi * i1;
+          wi = wr * i1 + wi * r1;
+          wr = nr;
+        }
+      });
+    } else if constexpr (TL > 1) {
       sfor<1, M>([&](auto k) {
         constexpr int kk = CV(k);
-        T wr = T(1), wi = T(0);
+        T wr, wi;
         if constexpr (TL == 2) {
           constexpr T r1 = Tw<T, N, DIR>::re(kk), i1 = Tw<T, N, DIR>::im(kk);
           wr = t ? r1 : T(1);
           wi = t ? i1 : T(0);
-        } else if constexpr (TL == 8) {
-          // W_N^{t k} for the lane's t in 0..7 (compile-time values, runtime select)
-          wr = T(1);
-          wi = T(0);
-          sfor<1, 8>([&](auto j) {
-            constexpr T rj = Tw<T, N, DIR>::re(CV(j) * kk), ij = Tw<T, N, DIR>::im(CV(j) * kk);
-            if (t == CV(j)) {
-              wr = rj;
-              wi = ij;
-            }
-          });
         } else {
           constexpr T r1 = Tw<T, N, DIR>::re(kk), i1 = Tw<T, N, DIR>::im(kk);
           constexpr T r2 = Tw<T, N, DIR>::re(2 * kk), i2 = Tw<T, N, DIR>::im(2 * kk);
@@ -258,11 +267,13 @@ struct LineFFT {
     }
   }
 
-  // radix-2 butterfly across lanes (xor mask): lower lane gets own+other, upper other-own
+  // radix-2 butterfly across lanes (xor mask): lower lane gets own+other, upper other-own,
+  // both as other + sign * own (one fused multiply-add per component)
   __device__ static __forceinline__ void xbfly(cplx<T> (&v)[M], int mask, bool upper) {
+    const T sg = upper ? T(-1) : T(1);
     sfor<0, M>([&](auto k) {
       cplx<T> o = shfl_xor_c(v[CV(k)], mask);
-      v[CV(k)] = upper ? csub(o, v[CV(k)]) : cadd(v[CV(k)], o);
+      v[CV(k)] = {T(fma(sg, v[CV(k)].re, o.re)), T(fma(sg, v[CV(k)].im, o.im))};
     });
   }
 
