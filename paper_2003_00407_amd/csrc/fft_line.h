@@ -211,9 +211,28 @@ __host__ __device__ constexpr int bitrev_lane(int t) {
 // ---------------------------------------------------------------------------
 // lane-group line FFT (device)
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ cplx<T> shfl_xor_c(cplx<T> v, int mask) {
-  return {__shfl_xor(v.re, mask), __shfl_xor(v.im, mask)};
+// value of lane (l xor MASK): within a quad (MASK 1, 2) by a DPP quad permute on the
+// vector ALU, else through the LDS crossbar (ds_bpermute; two row-shift DPP moves
+// with bank masks measured slower for MASK 4)
+template <int MASK, typename T>
+__device__ __forceinline__ T lane_xor(T v) {
+  if constexpr (MASK == 1 || MASK == 2) {
+    constexpr int ctrl = MASK == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    if constexpr (sizeof(T) == 8) {
+      const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+      const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+      return __hiloint2double(hi, lo);
+    } else {
+      return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+    }
+  } else {
+    return __shfl_xor(v, MASK);
+  }
+}
+
+template <int MASK, typename T>
+__device__ __forceinline__ cplx<T> shfl_xor_c(cplx<T> v) {
+  return {lane_xor<MASK>(v.re), lane_xor<MASK>(v.im)};
 }
 
 template <typename T, int N, int TL>
@@ -269,10 +288,11 @@ struct LineFFT {
 
   // radix-2 butterfly across lanes (xor mask): lower lane gets own+other, upper other-own,
   // both as other + sign * own (one fused multiply-add per component)
-  __device__ static __forceinline__ void xbfly(cplx<T> (&v)[M], int mask, bool upper) {
+  template <int MASK>
+  __device__ static __forceinline__ void xbfly(cplx<T> (&v)[M], bool upper) {
     const T sg = upper ? T(-1) : T(1);
     sfor<0, M>([&](auto k) {
-      cplx<T> o = shfl_xor_c(v[CV(k)], mask);
+      cplx<T> o = shfl_xor_c<MASK>(v[CV(k)]);
       v[CV(k)] = {T(fma(sg, v[CV(k)].re, o.re)), T(fma(sg, v[CV(k)].im, o.im))};
     });
   }
@@ -291,33 +311,33 @@ struct LineFFT {
   template <int DIR>
   __device__ static __forceinline__ void cross_lane(cplx<T> (&v)[M], int t) {
     if constexpr (TL == 2) {
-      xbfly(v, 1, t & 1);
+      xbfly<1>(v, t & 1);
     } else if constexpr (TL == 8) {
       // radix-2 network over the three lane bits (decimation in frequency forward,
       // its transpose with conjugate twiddles inverse); lane t holds index bitrev(t)
       if constexpr (DIR < 0) {
-        xbfly(v, 4, t & 4);
+        xbfly<4>(v, t & 4);
         w8_upper(v, t, -1);
-        xbfly(v, 2, t & 2);
+        xbfly<2>(v, t & 2);
         if ((t & 3) == 3) sfor<0, M>([&](auto k) { v[CV(k)] = cmul_i<-1>(v[CV(k)]); });
-        xbfly(v, 1, t & 1);
+        xbfly<1>(v, t & 1);
       } else {
-        xbfly(v, 1, t & 1);
+        xbfly<1>(v, t & 1);
         if ((t & 3) == 3) sfor<0, M>([&](auto k) { v[CV(k)] = cmul_i<+1>(v[CV(k)]); });
-        xbfly(v, 2, t & 2);
+        xbfly<2>(v, t & 2);
         w8_upper(v, t, +1);
-        xbfly(v, 4, t & 4);
+        xbfly<4>(v, t & 4);
       }
     } else if constexpr (TL == 4) {
       if constexpr (DIR < 0) {
-        xbfly(v, 2, t & 2);
+        xbfly<2>(v, t & 2);
         if (t == 3) sfor<0, M>([&](auto k) { v[CV(k)] = cmul_i<-1>(v[CV(k)]); });
-        xbfly(v, 1, t & 1);
+        xbfly<1>(v, t & 1);
       } else {
         // mirror of the forward network
-        xbfly(v, 1, t & 1);
+        xbfly<1>(v, t & 1);
         if (t == 3) sfor<0, M>([&](auto k) { v[CV(k)] = cmul_i<+1>(v[CV(k)]); });
-        xbfly(v, 2, t & 2);
+        xbfly<2>(v, t & 2);
       }
     }
   }
