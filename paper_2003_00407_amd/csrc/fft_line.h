@@ -286,6 +286,40 @@ struct LineFFT {
     }
   }
 
+  // the lane's root W_N^t of the forward direction (8 lanes per line), for kernels that
+  // select it once and pass it to forward() and inverse() (the inverse conjugates it)
+  __device__ static __forceinline__ cplx<T> root(int t) {
+    T r1 = T(1), i1 = T(0);
+    if constexpr (TL == 8) {
+      sfor<1, 8>([&](auto j) {
+        constexpr T rj = Tw<T, N, -1>::re(CV(j)), ij = Tw<T, N, -1>::im(CV(j));
+        if (t == CV(j)) {
+          r1 = rj;
+          i1 = ij;
+        }
+      });
+    }
+    return {r1, i1};
+  }
+
+  template <int DIR>
+  __device__ static __forceinline__ void lane_twiddle(cplx<T> (&v)[M], int t, cplx<T> w1) {
+    if constexpr (TL == 8) {
+      const T r1 = w1.re, i1 = DIR < 0 ? w1.im : -w1.im;
+      T wr = r1, wi = i1;
+      sfor<1, M>([&](auto k) {
+        v[CV(k)] = cmul(v[CV(k)], wr, wi);
+        if constexpr (CV(k) + 1 < M) {
+          const T nr = wr * r1 - wi * i1;
+          wi = wr * i1 + wi * r1;
+          wr = nr;
+        }
+      });
+    } else {
+      lane_twiddle<DIR>(v, t);
+    }
+  }
+
   // radix-2 butterfly across lanes (xor mask): lower lane gets own+other, upper other-own,
   // both as other + sign * own (one fused multiply-add per component)
   template <int MASK>
@@ -352,6 +386,18 @@ struct LineFFT {
   __device__ static __forceinline__ void inverse(cplx<T> (&v)[M], int t) {
     cross_lane<+1>(v, t);
     lane_twiddle<+1>(v, t);
+    dft_reg<T, M, +1>(v);
+  }
+
+  // the same with the lane's root w1 = root(t) selected once by the caller
+  __device__ static __forceinline__ void forward(cplx<T> (&v)[M], int t, cplx<T> w1) {
+    dft_reg<T, M, -1>(v);
+    lane_twiddle<-1>(v, t, w1);
+    cross_lane<-1>(v, t);
+  }
+  __device__ static __forceinline__ void inverse(cplx<T> (&v)[M], int t, cplx<T> w1) {
+    cross_lane<+1>(v, t);
+    lane_twiddle<+1>(v, t, w1);
     dft_reg<T, M, +1>(v);
   }
 };

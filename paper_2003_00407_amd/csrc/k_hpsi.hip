@@ -244,6 +244,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
   const int col = blockIdx.x * (256 / TL) + threadIdx.x / TL;
   const int t = threadIdx.x % TL;
   if (col >= nxy) return;  // whole lane groups leave together
+  const cplx<T> wz = FZ::root(t);   // one root selection for both transforms
 
   cplx<T> v[M];
   if constexpr (MODE == ZM_HPSI) {
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       v[CV(i)] = {in.a[o], in.b ? in.b[o] : T(0)};
     });
-    FZ::forward(v, t);
+    FZ::forward(v, t, wz);
     const T gzs = T(E.kz / NZ);
     sfor<0, M>([&](auto i) {
       const int f = signed_freq(FZ::freq(CV(i), t), NZ);
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       v[CV(i)].re *= g;
       v[CV(i)].im *= g;
     });
-    FZ::inverse(v, t);
+    FZ::inverse(v, t, wz);
     PairCols<T> out = pair_cols<T>(E, A.out_blk, pair, ncols);
     sfor<0, M>([&](auto i) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
@@ -274,7 +275,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       v[CV(i)] = {w.a[o], w.b[o]};
     });
-    FZ::forward(v, t);
+    FZ::forward(v, t, wz);
     const int KP = E.kmax3 + 2;
     const double* ek = E.small + SmallLayout::vec(KP) + VS_EKIN * KP;
     const double ea = ek[2 * pair];
@@ -292,7 +293,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       v[CV(i)].re *= kf;
       v[CV(i)].im *= kf;
     });
-    FZ::inverse(v, t);
+    FZ::inverse(v, t, wz);
     sfor<0, M>([&](auto i) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       w.a[o] = v[CV(i)].re;
