@@ -1603,22 +1603,48 @@ static bool set_lds_limit(const void* fn, int bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
 }
 
+// FP32 Grams stage 18, 26 or 36 values per thread (up to 288, 416, 576 columns); the
+// wider stagings exist only for up to 6 and 4 output blocks per wave, where they fit
+// the registers without spilling
+template <int MB>
+static void gram_attrs() {
+  set_lds_limit((const void*)k_gram<double, MB>, 96000);
+  set_lds_limit((const void*)k_gram_bf16<MB, 18>, 144000);
+  if constexpr (MB <= 6) set_lds_limit((const void*)k_gram_bf16<MB, 26>, 144000);
+  if constexpr (MB <= 4) set_lds_limit((const void*)k_gram_bf16<MB, 36>, 144000);
+}
+
+template <int MB>
+static int launch_gram_bf16(dim3 g, size_t lds, hipStream_t s, const GramArgs& ga, int nc) {
+  if (nc <= 288) {
+    hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g, dim3(GP_THREADS), lds, s, ga);
+    return DG_OK;
+  }
+  if constexpr (MB <= 6) {
+    if (nc <= 416) {
+      hipLaunchKernelGGL((k_gram_bf16<MB, 26>), g, dim3(GP_THREADS), lds, s, ga);
+      return DG_OK;
+    }
+  }
+  if constexpr (MB <= 4) {
+    hipLaunchKernelGGL((k_gram_bf16<MB, 36>), g, dim3(GP_THREADS), lds, s, ga);
+    return DG_OK;
+  }
+  set_error("Gram: no FP32 staging variant for " + std::to_string(nc) + " columns at " + std::to_string(MB) +
+            " blocks per wave");
+  return DG_ERR_SHAPE;
+}
+
 // dynamic-LDS limits of every kernel variant, set once before any launch (and so
 // never from inside a stream capture)
 void init_kernel_attributes() {
   static const bool done = [] {
-#define DG_GRAM_ATTR(MB)                                    \
-  set_lds_limit((const void*)k_gram<double, MB>, 96000); \
-  set_lds_limit((const void*)k_gram_bf16<MB, 18>, 144000); \
-  set_lds_limit((const void*)k_gram_bf16<MB, 26>, 144000); \
-  set_lds_limit((const void*)k_gram_bf16<MB, 36>, 144000);
-    DG_GRAM_ATTR(1)
-    DG_GRAM_ATTR(2)
-    DG_GRAM_ATTR(3)
-    DG_GRAM_ATTR(4)
-    DG_GRAM_ATTR(6)
-    DG_GRAM_ATTR(8)
-#undef DG_GRAM_ATTR
+    gram_attrs<1>();
+    gram_attrs<2>();
+    gram_attrs<3>();
+    gram_attrs<4>();
+    gram_attrs<6>();
+    gram_attrs<8>();
     set_lds_limit((const void*)k_rr_lds<true>, kRRLdsBytes);
     return true;
   }();
@@ -1676,18 +1702,13 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   auto launch = [&](int ns) -> int {
     ga.nsplit = ns;
     dim3 g1(groups, ns, c.n_elem);
-#define DG_GRAM_CASE(MB)                                                                   \
-  case MB:                                                                                 \
-    if (prec == DG_FP64) {                                                                 \
-      hipLaunchKernelGGL((k_gram<double, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga);   \
-    } else {                                                                               \
-      if (nc <= 288)                                                                       \
-        hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
-      else if (nc <= 416)                                                                  \
-        hipLaunchKernelGGL((k_gram_bf16<MB, 26>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
-      else                                                                                 \
-        hipLaunchKernelGGL((k_gram_bf16<MB, 36>), g1, dim3(GP_THREADS), lds_bf16, c.stream, ga); \
-    }                                                                                      \
+#define DG_GRAM_CASE(MB)                                                                 \
+  case MB:                                                                               \
+    if (prec == DG_FP64) {                                                               \
+      hipLaunchKernelGGL((k_gram<double, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga); \
+    } else if (int st = launch_gram_bf16<MB>(g1, lds_bf16, c.stream, ga, nc)) {          \
+      return st;                                                                         \
+    }                                                                                    \
     break;
     switch (maxb) {
       DG_GRAM_CASE(1)
