@@ -12,6 +12,7 @@
 //  * Residual norms ||H x_i - theta_i x_i|| and the preconditioner energy.
 #include "dg_internal.h"
 #include "tridiag.h"
+#include "wave_ops.h"
 
 #include <algorithm>
 #include <cstdio>
@@ -379,29 +380,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
-}
-
-// Wave sum with DPP row operations and lane reads (no LDS permutes); every lane of
-// the wave must be active.  Within each row of 16 lanes: xor-1 and xor-2 quad
-// permutes, then the half-row and row mirrors; the four row sums are then read
-// from lanes 0, 16, 32, 48 and added in a fixed order (result uniform).
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double lane_read(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_mov<0x141>(v);   // row_half_mirror
-  v += dpp_mov<0x140>(v);   // row_mirror
-  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // sum over the block, result broadcast to every thread (fixed order)

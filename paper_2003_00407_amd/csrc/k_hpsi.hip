@@ -17,6 +17,7 @@
 // line; an odd last column pairs with zero.
 #include "dg_internal.h"
 #include "fft_line.h"
+#include "wave_ops.h"
 
 #include <algorithm>
 
@@ -352,16 +353,14 @@ __global__ void __launch_bounds__(256) k_nl_overlap(NlArgs A) {
       }
     }
   }
-  // block reduction in a fixed order: wave butterflies, then across waves
+  // block reduction in a fixed order: DPP wave sums, then across waves
   __shared__ double red[4][4 * kNlCols];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int j = 0; j < kNlCols; ++j) {
-      double v = acc[q][j];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      const double v = wave_sum_dpp(acc[q][j]);
       if (lane == 0) red[wv][q * kNlCols + j] = v;
     }
   __syncthreads();
