@@ -222,6 +222,10 @@ int launch_check(Ctx& c, int* active, double tol);
 void init_kernel_attributes();
 int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                      long long out_off, int rows_e, int sym);
+// symmetric S^T T (to out_off_st) and S^T S (to out_off_ss) from one staging of [S | T]
+// where the shapes allow it, else as two Grams
+int launch_gram_pair(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT, long long out_off_st,
+                     long long out_off_ss, const int* active);
 int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed);
 int launch_copy_packed(Ctx& c, int prec, int blk, const double* ptr, const long long* off, int ncol,
                        int to_packed);

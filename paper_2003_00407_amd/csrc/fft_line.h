@@ -218,12 +218,13 @@ template <int MASK, typename T>
 __device__ __forceinline__ T lane_xor(T v) {
   if constexpr (MASK == 1 || MASK == 2) {
     constexpr int ctrl = MASK == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    // every lane reads a lane of its own quad, so no "old" value is needed
     if constexpr (sizeof(T) == 8) {
-      const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-      const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+      const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, true);
+      const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, true);
       return __hiloint2double(hi, lo);
     } else {
-      return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+      return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, true));
     }
   } else {
     return __shfl_xor(v, MASK);

@@ -70,6 +70,8 @@ struct GramArgs {
   double* part;        // per element region of part_stride doubles
   long long part_stride;
   int part_ld;         // leading dim of a partial matrix
+  int pair;            // 1: also S^T S (symmetric) from the same staged S columns
+  long long part_pair; // offset (doubles) of the S^T S partials inside an element's region
 };
 
 constexpr int GP_THREADS = 512;
@@ -100,7 +102,8 @@ __device__ __forceinline__ void gram_block(int b, int bi, int bj, int sym, int& 
   q = p + b;
 }
 
-template <typename T, int MAXB>
+// PF: staged values per thread and step (32 columns per pass of the workgroup)
+template <typename T, int MAXB, int PF>
 __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
   const int e = blockIdx.z;
   const ElemDev& E = A.elems[e];
@@ -110,8 +113,9 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
   const int ni = A.S.nb * kS, nj = A.T.nb * kT;
   const int bi = (ni + 15) >> 4, bj = (nj + 15) >> 4;
   const int nblk = A.sym ? bi * (bi + 1) / 2 : bi * bj;
+  const int nblk_all = A.pair ? 2 * nblk : nblk;
   const int b0 = blockIdx.x * A.cap;
-  if (b0 >= nblk) return;
+  if (b0 >= nblk_all) return;
   const int split = blockIdx.y;
   const int nrows = nrows_of(E, A.rows_e);
   const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GP_R - 1) / GP_R * GP_R;
@@ -132,30 +136,34 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
     }
     cp[c] = ptr;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // this wave's output blocks: b0 + w + 8 t
+  // the wave index is uniform: the block bookkeeping below stays in scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // this wave's output blocks: b0 + w + 8 t; in pair mode blocks nblk .. 2 nblk - 1 are
+  // those of S^T S (B operand from the S columns)
   int bp[MAXB], bq[MAXB];
   bool bv[MAXB];
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
     const int b = b0 + w + 8 * t;
-    bv[t] = b < nblk && b < b0 + A.cap;
+    bv[t] = b < nblk_all && b < b0 + A.cap;
+    const int second = b >= nblk;
     int p = 0, q = 0;
-    if (bv[t]) gram_block(b, bi, bj, A.sym, p, q);
-    bp[t] = p * 16 + (lane & 15);
-    bq[t] = toff + q * 16 + (lane & 15);
+    if (bv[t]) gram_block(b - second * nblk, bi, bj, A.sym, p, q);
+    bp[t] = p * 16;
+    bq[t] = (second ? 0 : toff) + q * 16;
   }
+  const int l16 = lane & 15;
   d4v acc[MAXB];
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
   __syncthreads();
   // staging map: thread -> grid row (tid % 16) of columns tid / 16 + 32 u
   const int srow = threadIdx.x & (GP_R - 1), scol = threadIdx.x >> 4;
-  double pre[GP_PF];
+  double pre[PF];
   auto load = [&](int rbase) {
     const int rr = rbase + srow;
 #pragma unroll
-    for (int u = 0; u < GP_PF; ++u) {
+    for (int u = 0; u < PF; ++u) {
       const int c = scol + 32 * u;
       double v = 0.0;
       if (c < nc) {
@@ -169,7 +177,7 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
   for (int r = r0; r < r1; r += GP_R) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < GP_PF; ++u) {
+    for (int u = 0; u < PF; ++u) {
       const int c = scol + 32 * u;
       if (c < nc) sm[srow * pitch + c] = pre[u];
     }
@@ -180,18 +188,20 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
       const int rowoff = (ks * 4 + (lane >> 4)) * pitch;
 #pragma unroll
       for (int t = 0; t < MAXB; ++t)
-        if (bv[t]) acc[t] = mfma16x16x4(sm[rowoff + bp[t]], sm[rowoff + bq[t]], acc[t]);
+        if (bv[t]) acc[t] = mfma16x16x4(sm[rowoff + l16 + bp[t]], sm[rowoff + l16 + bq[t]], acc[t]);
     }
   }
   double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
     if (!bv[t]) continue;
-    const int i0 = bp[t] - (lane & 15), j = bq[t] - toff;
+    const bool second = b0 + w + 8 * t >= nblk;
+    double* o = second ? out + A.part_pair : out;
+    const int i0 = bp[t], j = bq[t] + l16 - (second ? 0 : toff);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + (lane >> 4) + 4 * q;
-      if (i < ni && j < nj) out[(size_t)i * A.part_ld + j] = acc[t][q];
+      if (i < ni && j < (second ? ni : nj)) o[(size_t)i * A.part_ld + j] = acc[t][q];
     }
   }
 }
@@ -1586,7 +1596,12 @@ static bool set_lds_limit(const void* fn, int bytes) {
 // the registers without spilling
 template <int MB>
 static void gram_attrs() {
-  set_lds_limit((const void*)k_gram<double, MB>, 96000);
+  set_lds_limit((const void*)k_gram<double, MB, 9>, 96000);
+  set_lds_limit((const void*)k_gram<double, MB, 18>, 96000);
+  if constexpr (MB == 8) {
+    set_lds_limit((const void*)k_gram<double, 12, 9>, 96000);
+    set_lds_limit((const void*)k_gram<double, 12, 18>, 96000);
+  }
   set_lds_limit((const void*)k_gram_bf16<MB, 18>, 144000);
   if constexpr (MB <= 6) set_lds_limit((const void*)k_gram_bf16<MB, 26>, 144000);
   if constexpr (MB <= 4) set_lds_limit((const void*)k_gram_bf16<MB, 36>, 144000);
@@ -1629,8 +1644,10 @@ void init_kernel_attributes() {
   (void)done;
 }
 
+// pair: also S^T S (to out_off_ss) from the same staging of [S | T]
 static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
-                     long long out_off, const int* active, int rows_e, int sym) {
+                     long long out_off, const int* active, int rows_e, int sym, bool pair = false,
+                     long long out_off_ss = 0) {
   int ks, kt, maxN, maxE;
   max_dims(c, kS, &ks, &maxN, &maxE);
   max_dims(c, kT, &kt, &maxN, &maxE);
@@ -1643,52 +1660,83 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   const int nc = bi * 16 + (same ? 0 : bj * 16);
   if (nc > GP_MAXCOL) { set_error("Gram: more columns than one workgroup stages"); return DG_ERR_SHAPE; }
   const int nblk = sym ? bi * (bi + 1) / 2 : bi * bj;
+  const long long part_sq = (long long)c.gram_part_ld * c.gram_part_ld;
+  if (pair) {
+    // one staging for both products (FP64, symmetric, T != S) when the doubled block
+    // list takes at most two workgroups per row panel (each stages [S | T]; measured
+    // slower than two Grams beyond that) and the partial area holds both; else two
+    // separate Grams
+    const bool fits = prec == DG_FP64 && sym && !same && 2 * nblk <= 2 * 8 * 12 &&
+                      c.gram_part_stride >= 2 * part_sq;
+    if (!fits) {
+      if (int st = gram_impl(c, prec, S, kS, S, kS, out_off_ss, active, rows_e, sym)) return st;
+      return gram_impl(c, prec, S, kS, T, kT, out_off, active, rows_e, sym);
+    }
+  }
+  const int nblk_all = pair ? 2 * nblk : nblk;
   // output blocks per wave: the smallest instantiated count that covers the result,
   // else 8 (larger results take several workgroups, each re-reading the columns)
   // (FP32 data with 289..416 staged columns: at most 6, which keeps the 26 staged values
-  // per thread and the accumulators in registers)
-  static const int kMaxbList[] = {1, 2, 3, 4, 6, 8};
-  const int maxb_top = prec == DG_FP64 || nc <= 288 ? 8 : (nc <= 416 ? 6 : 4);
+  // per thread and the accumulators in registers; 12 only for the FP64 pair)
+  static const int kMaxbList[] = {1, 2, 3, 4, 6, 8, 12};
+  const int maxb_top = pair ? 12 : (prec == DG_FP64 || nc <= 288 ? 8 : (nc <= 416 ? 6 : 4));
   int maxb = maxb_top;
   for (int m : kMaxbList)
-    if (m <= maxb_top && 8 * m >= nblk) {
+    if (m <= maxb_top && 8 * m >= nblk_all) {
       maxb = m;
       break;
     }
   const int cap = 8 * maxb;
-  const int groups = (nblk + cap - 1) / cap;
+  const int groups = (nblk_all + cap - 1) / cap;
   // row-range split: about 1024 workgroups over the launch, at least 256 rows each; the
-  // autotuner below may replace it by half or twice that for this Gram shape
-  const int split_cap = std::max(1, std::min(c.gram_max_split, rows / 256));
+  // autotuner below may replace it by half or twice that for this Gram shape (the pair
+  // keeps two sets of partials)
+  const int split_cap = std::max(1, std::min(pair ? (int)(c.gram_part_stride / (2 * part_sq)) : c.gram_max_split,
+                                             rows / 256));
   int nsplit = std::max(1, std::min(split_cap, (1024 + groups * c.n_elem - 1) / (groups * c.n_elem)));
-  const long long key = (((((long long)prec * 1024 + maxni) * 1024 + maxnj) * 2 + sym) * 2 + (same ? 1 : 0)) * 2 +
-                        rows_e;
+  const long long key =
+      ((((((long long)prec * 1024 + maxni) * 1024 + maxnj) * 2 + sym) * 2 + (same ? 1 : 0)) * 2 + rows_e) * 2 +
+      (pair ? 1 : 0);
   auto tuned = c.gram_split_table.find(key);
   if (tuned != c.gram_split_table.end()) nsplit = tuned->second;
   GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, rows_e, sym, same ? 1 : 0, cap, c.gram_part,
-              c.gram_part_stride, c.gram_part_ld};
+              c.gram_part_stride, c.gram_part_ld, pair ? 1 : 0, 0};
   double flops = 0.0;
   for (int e = 0; e < c.n_elem; ++e) {
     if (active && !c.active_host.empty() && !c.active_host[e]) continue;
     const int ke = kS > 0 ? kS : (kS == 0 ? c.K[e] : c.J[e]);
     const int kt = kT > 0 ? kT : (kT == 0 ? c.K[e] : c.J[e]);
     const double r = rows_e ? (double)c.en[0][e] * c.en[1][e] * c.en[2][e] : (double)c.N[e];
-    flops += 2.0 * r * (S.nb * ke) * (T.nb * kt);
+    flops += 2.0 * r * (S.nb * ke) * (T.nb * kt) * (pair ? 2.0 : 1.0);
   }
   const size_t lds = (size_t)GP_R * (nc + 1) * sizeof(double) + (size_t)nc * sizeof(void*);
   const size_t lds_bf16 = (size_t)3 * nc * GB_PITCH * 2 + (size_t)nc * sizeof(void*);
   auto launch = [&](int ns) -> int {
     ga.nsplit = ns;
+    ga.part_pair = ns * part_sq;
     dim3 g1(groups, ns, c.n_elem);
 #define DG_GRAM_CASE(MB)                                                                 \
   case MB:                                                                               \
     if (prec == DG_FP64) {                                                               \
-      hipLaunchKernelGGL((k_gram<double, MB>), g1, dim3(GP_THREADS), lds, c.stream, ga); \
+      if (nc <= 288)                                                                     \
+        hipLaunchKernelGGL((k_gram<double, MB, 9>), g1, dim3(GP_THREADS), lds, c.stream, ga); \
+      else                                                                               \
+        hipLaunchKernelGGL((k_gram<double, MB, 18>), g1, dim3(GP_THREADS), lds, c.stream, ga); \
     } else if (int st = launch_gram_bf16<MB>(g1, lds_bf16, c.stream, ga, nc)) {          \
       return st;                                                                         \
     }                                                                                    \
     break;
     switch (maxb) {
+      case 12:
+        if (prec != DG_FP64) {
+          set_error("Gram: unsupported block count");
+          return DG_ERR_SHAPE;
+        }
+        if (nc <= 288)
+          hipLaunchKernelGGL((k_gram<double, 12, 9>), g1, dim3(GP_THREADS), lds, c.stream, ga);
+        else
+          hipLaunchKernelGGL((k_gram<double, 12, 18>), g1, dim3(GP_THREADS), lds, c.stream, ga);
+        break;
       DG_GRAM_CASE(1)
       DG_GRAM_CASE(2)
       DG_GRAM_CASE(3)
@@ -1728,8 +1776,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     c.gram_split_table[key] = best_ns;
     nsplit = best_ns;
     if (c.log_level > 0)
-      fprintf(stderr, "[dg] gram autotune %dx%d sym=%d prec=%d: split %d (%.3f ms)\n", maxni, maxnj, sym, prec,
-              best_ns, best);
+      fprintf(stderr, "[dg] gram autotune %dx%d sym=%d prec=%d pair=%d: split %d (%.3f ms)\n", maxni, maxnj, sym,
+              prec, pair ? 1 : 0, best_ns, best);
   }
   TimedScope ts(c, TC_GRAM, flops);
   if (int st = launch(nsplit)) return st;
@@ -1737,6 +1785,11 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
                     c.gram_part_stride, c.gram_part_ld, out_off, 0};
   dim3 g2((maxni * maxnj + 255) / 256, c.n_elem);
   hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, c.stream, ra);
+  if (pair) {
+    GramReduceArgs rs{c.elems_dev, active, sym, S.nb, S.nb, kS, kS, nsplit, c.gram_part + nsplit * part_sq,
+                      c.gram_part_stride, c.gram_part_ld, out_off_ss, 0};
+    hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, c.stream, rs);
+  }
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -1749,6 +1802,11 @@ int launch_gram(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int 
 int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                      long long out_off, int rows_e, int sym) {
   return gram_impl(c, prec, S, kS, T, kT, out_off, nullptr, rows_e, sym);
+}
+
+int launch_gram_pair(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT, long long out_off_st,
+                     long long out_off_ss, const int* active) {
+  return gram_impl(c, prec, S, kS, T, kT, out_off_st, active, 0, 1, true, out_off_ss);
 }
 
 int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) {

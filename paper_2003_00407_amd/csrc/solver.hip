@@ -64,8 +64,7 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   ColSet S{nb, {B_X, B_W, B_P}};
   ColSet HS{nb, {B_HX, B_HW, B_HP}};
   // S^T S and S^T H S are symmetric (the latter in exact arithmetic): upper tiles, mirrored
-  if ((st = launch_gram(c, prec, S, KC_K, S, KC_K, small_code(0), active, 1))) return st;
-  if ((st = launch_gram(c, prec, S, KC_K, HS, KC_K, small_code(1), active, 1))) return st;
+  if ((st = launch_gram_pair(c, prec, S, KC_K, HS, KC_K, small_code(1), small_code(0), active))) return st;
   if ((st = launch_rr(c, nb, 0, 0, RR_GEN, active))) return st;
   // X' = S C (-> T0), P' = [W P] C_WP (-> T1); HX' = HS C, HP' = [HW HP] C_WP
   RotArgs ra{};

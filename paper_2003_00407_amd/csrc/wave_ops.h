@@ -10,10 +10,11 @@ namespace dg {
 // the wave must be active.  Within each row of 16 lanes: xor-1 and xor-2 quad
 // permutes, then the half-row and row mirrors; the four row sums are then read
 // from lanes 0, 16, 32, 48 and added in a fixed order (result uniform).
+// (CTRL patterns whose every lane reads a valid lane of its row: no "old" value)
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_read(double v, int l) {
