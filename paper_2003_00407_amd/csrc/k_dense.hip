@@ -968,39 +968,61 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     __syncthreads();
   }
   stamp(7);
-  // back-transform: z <- H_0 ... H_{m-3} z (lanes over rows); a wave carries four of
-  // its vectors through the reflectors together, so that their dot products and
-  // reductions overlap
-  {
-    constexpr int BV = 4;
-    for (int j0 = wv; j0 < nwant; j0 += BV * nw) {
-      double* z[BV];
-      bool on[BV];
-#pragma unroll
-      for (int b = 0; b < BV; ++b) {
-        const int j = j0 + b * nw;
-        on[b] = j < nwant;
-        z[b] = zl + (size_t)(on[b] ? j : j0) * np;
-      }
-      for (int kk = m - 3; kk >= 0; --kk) {
-        const double tau = stau[kk];
-        if (tau == 0.0) continue;
-        const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
-        double dot[BV];
-#pragma unroll
-        for (int b = 0; b < BV; ++b) dot[b] = 0.0;
-        for (int i = lane; i < m - 1 - kk; i += 64) {
-          const double vi = v[i];
-#pragma unroll
-          for (int b = 0; b < BV; ++b) dot[b] += vi * z[b][kk + 1 + i];
+  if constexpr (kLds) {
+    // back-transform: z <- H_0 ... H_{m-3} z with eight lanes per vector (the dot
+    // product reduced within the lane group) and every vector at once: the reflectors
+    // are read-only, so the vectors need no barriers between reflectors
+    {
+      const int l8 = tid & 7;
+      for (int j = tid >> 3; j < nwant; j += nt >> 3) {
+        double* z = zl + (size_t)j * np;
+        for (int kk = m - 3; kk >= 0; --kk) {
+          const double tau = stau[kk];
+          if (tau == 0.0) continue;
+          const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
+          const int len = m - 1 - kk;
+          double dot = 0.0;
+          for (int i = l8; i < len; i += 8) dot += v[i] * z[kk + 1 + i];
+          dot = group8_sum(dot) * tau;
+          for (int i = l8; i < len; i += 8) z[kk + 1 + i] -= dot * v[i];
         }
+      }
+    }
+  } else {
+    // back-transform: z <- H_0 ... H_{m-3} z (lanes over rows); a wave carries four of
+    // its vectors through the reflectors together, so that their dot products and
+    // reductions overlap
+    {
+      constexpr int BV = 4;
+      for (int j0 = wv; j0 < nwant; j0 += BV * nw) {
+        double* z[BV];
+        bool on[BV];
 #pragma unroll
-        for (int b = 0; b < BV; ++b) dot[b] = wave_sum_dpp(dot[b]) * tau;
-        for (int i = lane; i < m - 1 - kk; i += 64) {
-          const double vi = v[i];
+        for (int b = 0; b < BV; ++b) {
+          const int j = j0 + b * nw;
+          on[b] = j < nwant;
+          z[b] = zl + (size_t)(on[b] ? j : j0) * np;
+        }
+        for (int kk = m - 3; kk >= 0; --kk) {
+          const double tau = stau[kk];
+          if (tau == 0.0) continue;
+          const double* v = rl + refl_off(kk, m);   // rows kk+1 .. m-1
+          double dot[BV];
 #pragma unroll
-          for (int b = 0; b < BV; ++b)
-            if (on[b]) z[b][kk + 1 + i] -= dot[b] * vi;
+          for (int b = 0; b < BV; ++b) dot[b] = 0.0;
+          for (int i = lane; i < m - 1 - kk; i += 64) {
+            const double vi = v[i];
+#pragma unroll
+            for (int b = 0; b < BV; ++b) dot[b] += vi * z[b][kk + 1 + i];
+          }
+#pragma unroll
+          for (int b = 0; b < BV; ++b) dot[b] = wave_sum_dpp(dot[b]) * tau;
+          for (int i = lane; i < m - 1 - kk; i += 64) {
+            const double vi = v[i];
+#pragma unroll
+            for (int b = 0; b < BV; ++b)
+              if (on[b]) z[b][kk + 1 + i] -= dot[b] * vi;
+          }
         }
       }
     }

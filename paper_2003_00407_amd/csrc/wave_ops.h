@@ -30,4 +30,13 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
+
+// sum over each group of 8 consecutive lanes (all 8 active), the same value on every
+// lane of the group: two quad permutes, then the xor-4 partner through ds_bpermute
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  return v + __shfl_xor(v, 4);
+}
+
 }  // namespace dg
