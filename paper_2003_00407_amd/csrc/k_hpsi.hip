@@ -32,6 +32,16 @@ __device__ __forceinline__ const float* vptr<float>(const ElemDev& E) { return E
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return (2 * k < n) ? k : k - n; }
 
+// 1/q from the hardware reciprocal (FP64: two Newton steps, a few ulps; FP32: one ulp)
+__device__ __forceinline__ double fast_recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double t = fma(-q, r, 1.0);
+  r = fma(r, t, r);
+  t = fma(-q, r, 1.0);
+  return fma(r, t, r);
+}
+__device__ __forceinline__ float fast_recip(float q) { return __builtin_amdgcn_rcpf(q); }
+
 enum PlaneMode { PM_HPSI = 0, PM_TFWD = 1, PM_TINV = 2 };
 
 struct PlaneArgs {
@@ -290,7 +300,8 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       const int f = signed_freq(FZ::freq(CV(i), t), NZ);
       const T x = (gxy + T(E.kz) * T(f * f)) * inv_e;
       const T num = T(27) + x * (T(18) + x * (T(12) + T(8) * x));
-      const T kf = norm * num / (num + T(16) * x * x * x * x);
+      const T x2 = x * x;
+      const T kf = norm * num * fast_recip(num + T(16) * x2 * x2);
       v[CV(i)].re *= kf;
       v[CV(i)].im *= kf;
     });
