@@ -101,7 +101,7 @@ typedef struct {
   double tol;          /* converged when max_i ||H x_i - theta_i x_i||_2 <= tol (Ha)  */
                        /* over the J_k wanted states of every element                */
   double tol_mixed;    /* DG_MIXED: residual at which the FP32 stage hands over to    */
-                       /* FP64 refinement (<= 0: 1e-4)                                */
+                       /* FP64 refinement (<= 0: 3e-5)                                */
   int32_t max_iter;    /* iteration cap per stage                                     */
   int32_t cheb_degree; /* DG_CHFSI filter degree m                                    */
   const double *x0_dev;/* packed initial blocks, N_k x (J_k + guards) per element     */

@@ -342,7 +342,7 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
                                 : run_chfsi(c, DG_FP64, p->tol, p->max_iter, p->cheb_degree, it1.data(), &done);
     if (st < 0) return st;
   } else {
-    const double tmp = p->tol_mixed > 0.0 ? p->tol_mixed : 1e-4;
+    const double tmp = p->tol_mixed > 0.0 ? p->tol_mixed : 3e-5;
     if ((st = launch_copy_packed(c, DG_FP32, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
     st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, it1.data(), &done)
                                 : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree,

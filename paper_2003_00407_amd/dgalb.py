@@ -192,7 +192,7 @@ class Elements:
         return y
 
     def solve(self, x0, method: int = DG_LOBPCG, precision: int = DG_FP64, tol: float = 1e-8,
-              tol_mixed: float = 1e-4, max_iter: int = 300, cheb_degree: int = 16, graph_iters: int = 0):
+              tol_mixed: float = 3e-5, max_iter: int = 300, cheb_degree: int = 16, graph_iters: int = 0):
         """Lowest J_k eigenpairs of every element; returns (eig, resid, iters, status)."""
         torch = self.torch
         if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
