@@ -36,11 +36,14 @@ CLASS_KERNEL = {"plane": "k_plane", "zcol": "k_zcol", "nonlocal": "k_nl_", "tete
 # on: `traffic` is reported null once the file's SHA-256 differs.
 PMC_TRAFFIC = {
     "rayleigh_ritz": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-                      "sha256": "e33858432bec4fd239e4897c6d2df854758a1835d8fb14dd9322b75c64ff2da9",
-                      "bytes_per_launch": 4004817},
+                      "sha256": "aa2653736a2e980afa53a0db438b9201a232bed557301bca9f82e5f14c3000fa",
+                      "bytes_per_launch": 3987693},
     "rotate": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-               "sha256": "e33858432bec4fd239e4897c6d2df854758a1835d8fb14dd9322b75c64ff2da9",
-               "bytes_per_launch": 795797470},
+               "sha256": "aa2653736a2e980afa53a0db438b9201a232bed557301bca9f82e5f14c3000fa",
+               "bytes_per_launch": 792666907},
+    "gram": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
+             "sha256": "aa2653736a2e980afa53a0db438b9201a232bed557301bca9f82e5f14c3000fa",
+             "bytes_per_launch": 1005229331},
 }
 
 
