@@ -159,6 +159,9 @@ class Elements:
         self._arena_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = C.c_void_p(0)
+        # held by the instance: module globals may already be cleared when the
+        # destructor runs at interpreter exit
+        self._destroy = _lib.dg_destroy
         _check(_lib.dg_create_elements(C.byref(self.ctx), self.hd.n, self.hd.arr, C.byref(self.opt),
                                        C.c_void_p(self._arena_ptr), C.c_size_t(int(nbytes.value)),
                                        C.c_void_p(self.stream.cuda_stream)), "dg_create_elements")
@@ -167,7 +170,7 @@ class Elements:
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
-            _lib.dg_destroy(ctx)
+            self._destroy(ctx)
             self.ctx = C.c_void_p(0)
 
     # ---- layout helpers
