@@ -752,6 +752,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   const int m = n;
   __shared__ int skip;
   __shared__ double pq[2][kTriMax];
+  static_assert(kRRThreads == 512, "the product p = tau A v splits the rows between two sets of 256 threads");
   for (int kk = 0; kk < m - 2; ++kk) {
     const int mr = m - kk - 1;
     if (wv == 0) {
@@ -1779,7 +1780,14 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     const int cand[3] = {nsplit, std::max(1, nsplit / 2), std::min(split_cap, nsplit * 2)};
     float best = 1e30f, base = 1e30f;
     int best_ns = nsplit;
-    hipEvent_t ev[2];
+    struct Events {   // destroyed on every return path
+      hipEvent_t e[2] = {nullptr, nullptr};
+      ~Events() {
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } evs;
+    hipEvent_t* ev = evs.e;
     DG_HIP(hipEventCreate(&ev[0]));
     DG_HIP(hipEventCreate(&ev[1]));
     for (int ci = 0; ci < 3; ++ci) {
@@ -1800,8 +1808,6 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
         best_ns = cand[ci];
       }
     }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     c.gram_split_table[key] = best_ns;
     nsplit = best_ns;
     if (c.log_level > 0)
