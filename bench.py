@@ -174,7 +174,7 @@ def make_x0(cfg, E, D, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+        print(f"bench.py: the benchmark runs on one GPU only (--gpus {args.gpus} requested); "
               "the element batch would shard across GPUs by whole elements with no communication, "
               "which is not measured here.", file=sys.stderr)
         sys.exit(2)
