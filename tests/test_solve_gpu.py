@@ -197,3 +197,31 @@ def test_captured_graph_iterations(precision):
         a = X0[off[k]:off[k + 1]].reshape(el.n_states, el.npts).T
         b = X1[off[k]:off[k + 1]].reshape(el.n_states, el.npts).T
         assert oalb.max_principal_angle(a, b) < 1e-6
+
+
+def test_gram_split_tuning_keeps_results(monkeypatch, capfd):
+    """The Gram row-split autotuner only changes how the row panels are grouped before
+    the fixed-order reduction: a tuned run (which logs its choices) reaches the
+    eigenvalues and subspaces of a run at the default split."""
+    from paper_2003_00407_amd import dgalb as D
+    els = W.make_config("c2").elements[:4]
+    monkeypatch.setenv("DG_TUNE", "0")
+    E0, eig0, res0, it0, st0 = _solve(els, tol=1e-8, n_streams=1)
+    monkeypatch.setenv("DG_TUNE", "1")
+    monkeypatch.setenv("DG_LOG", "1")
+    E1, eig1, res1, it1, st1 = _solve(els, tol=1e-8, n_streams=1)
+    monkeypatch.delenv("DG_LOG")
+    log = capfd.readouterr().err
+    tuned = [ln for ln in log.splitlines() if ln.startswith("[dg] gram autotune")]
+    print("\n".join(tuned))
+    print("iterations", it0, it1)
+    assert tuned, "the tuned run logged no split choice"
+    assert st0 == 0 and st1 == 0
+    X0 = unpack(E0.vectors().cpu().numpy(), E0.offsets(D.DG_OFF_VEC), [e.npts for e in els],
+                [e.n_states for e in els])
+    X1 = unpack(E1.vectors().cpu().numpy(), E1.offsets(D.DG_OFF_VEC), [e.npts for e in els],
+                [e.n_states for e in els])
+    for k in range(len(els)):
+        assert max(res0[k].max(), res1[k].max()) <= 1e-8
+        assert np.max(np.abs(eig0[k] - eig1[k])) < 1e-10
+        assert oalb.max_principal_angle(X0[k], X1[k]) < 1e-6
