@@ -35,6 +35,16 @@
  *    stream waits for it, so the caller sees one stream.  The library never
  *    allocates device memory: the caller provides one arena of the size
  *    dg_query_workspace reports.
+ *  - Environment variables read by dg_create_elements (tuning and
+ *    diagnostics): DG_STREAMS (element groups when n_streams <= 0);
+ *    DG_TUNE=0 (no timing of the Gram row split, the size heuristic is
+ *    used); DG_LOG (progress on stderr: 1 residuals per iteration and the
+ *    tuner's choices, 2 Rayleigh-Ritz phase times, 3 Cholesky pivots; any
+ *    level > 0 turns graph capture off); DG_RR_ORTOL (inverse-iteration
+ *    cluster tolerance relative to ||T||, default 1e-5); DG_RR_DROP
+ *    (threshold on the scaled-overlap pivot below which a W or P column
+ *    leaves the basis; default 1e-8 in FP64, 1e-4 in the FP32 stage);
+ *    DG_ORTH_W=1 (W is made orthogonal to X before the projected problem).
  */
 #ifndef DG_ALB_H
 #define DG_ALB_H
