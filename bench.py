@@ -1,12 +1,16 @@
 #!/usr/bin/env python
 """Benchmark: batched ALB generation on one MI355X.
 
-One step = the whole hot path on one batch: seeded cold start -> LOBPCG to a
-residual of 1e-8 Ha on every element -> ALBs (restriction + orthonormalisation),
-for the 4x4 graphene-like slab (16 extended elements of 48x48x64, 40 states
-each, FP64).  The mixed-precision path (FP32 stage, FP64 refinement) is timed
-on the same batch and reported beside it, and so is a pass with all elements in
-one stream (kernel durations without overlap).
+One step = the whole hot path on one batch: a seeded cold start -> LOBPCG to a
+residual of 1e-8 Ha on every element -> ALBs (restriction + orthonormalisation).
+The headline workload is the uneven batch: 256 elements of the graphene-like slab
+with extended grids of 32x32x64, 48x48x64 and 64x64x64 points and 20-80 states,
+2 % vacancies, solved in FP64; every timed step must return DG_OK with every
+residual <= 1e-8.  Beside it: the mixed-precision path (FP32 stage + FP64
+refinement) on the same batch, a step with per-kernel HIP-event timing (the class
+table and the roofline of the dominant kernel), a step with all elements in one
+stream (kernel durations without overlap between element groups), and the oracle
+timed on the host cores on one element of the batch.
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region.
 """
@@ -24,27 +28,18 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix
 CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
 # kernel symbol of each timing class's main kernel (rocprofv3 names)
 CLASS_KERNEL = {"plane": "k_plane", "zcol": "k_zcol", "nonlocal": "k_nl_", "teter": "k_plane",
                 "gram": "k_gram", "rotate": "k_rotate", "rayleigh_ritz": "k_rr_lds", "other": "k_residual"}
+METRIC = "ALB element-solves/s + Hψ GB/s, mixed vs FP64 on one GPU at 1e-8 Ha eigen error"
 
 # HBM bytes per launch from `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of
-# `bench.py --steps 1 --warmup 0 --no-mixed --no-isolated --no-cpu-baseline --copy-probe-mib 1024`
-# on the C2 batch, scaled by what the counters read for the 1 GiB device copy of the same
-# run (profiles/c2_fp64_hbm_traffic.md).  Valid only for the kernel source they were taken
-# on: `traffic` is reported null once the file's SHA-256 differs.
-PMC_TRAFFIC = {
-    "rayleigh_ritz": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-                      "sha256": "19f84bf8edb687395f94fa0caae0bbab454419c92fba272ecc90d225115659fa",
-                      "bytes_per_launch": 3987692},
-    "rotate": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-               "sha256": "19f84bf8edb687395f94fa0caae0bbab454419c92fba272ecc90d225115659fa",
-               "bytes_per_launch": 792666642},
-    "gram": {"config": "c2", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-             "sha256": "19f84bf8edb687395f94fa0caae0bbab454419c92fba272ecc90d225115659fa",
-             "bytes_per_launch": 1005228684},
-}
+# the instrumented step (profiles/*_hbm_traffic.md), scaled by what the counters read
+# for a 1 GiB device copy of the same run.  Valid only for the kernel source and
+# workload they were taken on: `traffic` is reported null once the source differs.
+PMC_TRAFFIC = {}
 
 
 def parse():
@@ -52,12 +47,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--mixed-steps", type=int, default=2, help="timed mixed-precision steps (after one warm-up)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-isolated", action="store_true", help="skip the one-stream pass")
+    ap.add_argument("--no-instrumented", action="store_true", help="skip the per-kernel timing step")
+    ap.add_argument("--no-isolated", action="store_true", help="skip the one-stream step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8, help="oracle LOBPCG iterations in the CPU sample")
+    ap.add_argument("--budget-s", type=float, default=520.0,
+                    help="wall-clock budget: side legs that would end past it are skipped (and said so)")
     ap.add_argument("--method", default="lobpcg", choices=["lobpcg", "chfsi"])
     ap.add_argument("--cheb-degree", type=int, default=16)
     ap.add_argument("--graph-iters", type=int, default=0,
@@ -67,26 +65,51 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(E, x0, precision, steps, warmup, tol, torch, graph_iters=0, method=0, degree=16):
-    """Warm up, then time `steps` full solves + ALBs; returns timing and kernel stats."""
-    kw = dict(precision=precision, tol=tol, graph_iters=graph_iters, method=method, cheb_degree=degree)
-    for _ in range(warmup):
-        E.solve(x0, **kw)
-        E.make_alb()
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def one_step(E, x0, kw, tol, tag):
+    """One solve + ALBs; a step that does not reach tol everywhere is an error."""
+    from paper_2003_00407_amd import dgalb as D
+    eig, res, iters, st = E.solve(x0, **kw)
+    E.make_alb()
+    mr = float(res.max().item())
+    if st != D.DG_OK or not (mr <= tol):
+        raise SystemExit(f"bench.py: {tag} step ended with status {D.status_string(st)} and max residual "
+                         f"{mr:.3e} (tolerance {tol:g})")
+    return iters, mr
+
+
+def run_timed(E, x0, kw, steps, warmup, tol, torch, tag):
+    """Warm up, then time `steps` full solves + ALBs with per-kernel timing off."""
+    for i in range(warmup):
+        one_step(E, x0, kw, tol, tag)
+        log(f"{tag}: warm-up step {i + 1}/{warmup} done")
+    E.timing(enable=False, reset=True)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, mr, worst = None, 0.0, 0.0
+    for i in range(steps):
+        iters, mr = one_step(E, x0, kw, tol, tag)
+        worst = max(worst, mr)
+        log(f"{tag}: step {i + 1}/{steps} at {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return {"seconds": t1 - t0, "iters": iters, "max_resid": worst}
+
+
+def run_instrumented(E, x0, kw, tol, torch, tag):
+    """One step with HIP events around every launch group: per-class times and work."""
     E.timing(enable=True, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = None
-    res = None
-    for _ in range(steps):
-        eig, res, iters, st = E.solve(x0, **kw)
-        E.make_alb()
+    iters, mr = one_step(E, x0, kw, tol, tag)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    sec = time.perf_counter() - t0
     ms, launches, work = E.timing(enable=False, reset=True)
-    return {"seconds": t1 - t0, "iters": iters, "ms": ms, "launches": launches,
-            "work": work, "max_resid": float(res.max().item())}
+    return {"seconds": sec, "iters": iters, "ms": ms, "launches": launches, "work": work[:8],
+            "hpsi_alg_bytes": work[8], "max_resid": mr}
 
 
 def kernel_table(r):
@@ -111,7 +134,7 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def roofline_for(r, config, with_traffic=True):
+def roofline_for(r, config, with_traffic=True, mixed=False):
     """Roofline of the dominant kernel class (most GPU time) over a run's kernels."""
     i = int(np.argmax(r["ms"]))
     name = CLASSES[i]
@@ -120,9 +143,9 @@ def roofline_for(r, config, with_traffic=True):
     if i <= 3:       # HBM-bound passes: algorithmic bytes per launch / duration
         achieved = (w / n) / avg_s / 1e9
         peak, unit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
-    elif i <= 5:     # subspace GEMMs on FP64 MFMA: algorithmic flops per launch / duration
+    elif i <= 5:     # subspace GEMMs on the matrix cores: algorithmic flops per launch / duration
         achieved = (w / n) / avg_s / 1e12
-        peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "mfma"
+        peak, unit, bound = (BF16_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), "TFLOP/s", "mfma"
     else:            # small dense FP64, one workgroup per element: vector ALU
         achieved = (w / n) / avg_s / 1e12
         peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "alu"
@@ -136,31 +159,37 @@ def roofline_for(r, config, with_traffic=True):
             "work_per_launch": w / n}
 
 
-def hpsi_rate(r):
-    """H*psi GB/s: algorithmic bytes of the H*psi passes over their summed time."""
+def hpsi_rates(r):
+    """H*psi GB/s over the three H*psi classes: by the per-state count 2Ns + Ns/J +
+    nnz(s+4)/J (algorithmic), and by the passes' own minimal bytes."""
     ms = r["ms"][0] + r["ms"][1] + r["ms"][2]
-    by = r["work"][0] + r["work"][1] + r["work"][2]
-    return round(by / (ms / 1000.0) / 1e9, 2) if ms > 0 else None
+    if ms <= 0:
+        return None, None
+    alg = r["hpsi_alg_bytes"] / (ms / 1000.0) / 1e9
+    passes = (r["work"][0] + r["work"][1] + r["work"][2]) / (ms / 1000.0) / 1e9
+    return round(alg, 1), round(passes, 1)
 
 
-def cpu_baseline(cfg, n_iters_scale, cpu_iters):
-    """The oracle (plain NumPy/SciPy FP64) on a bounded sample: one element, a few LOBPCG iterations."""
+def cpu_baseline(cfg, tol):
+    """The oracle (plain NumPy/SciPy FP64) solving one element of the batch to tol."""
     import workloads as W
+    from oracle import alb as oalb
     from oracle import lobpcg as olob
     from oracle.planewave import n_workers
-    el = cfg.elements[5]
+    # the element of median cost N (J + g)^2 (a representative element of the batch)
+    cost = [e.npts * (e.n_states + W.guard_count(e.n_states)) ** 2 for e in cfg.elements]
+    k = int(np.argsort(cost)[len(cost) // 2])
+    el = cfg.elements[k]
     J = el.n_states
-    x0 = W.initial_block(el.npts, J + W.guard_count(J), cfg.x0_seed_base + 5).T
+    x0 = W.initial_block(el.npts, J + W.guard_count(J), cfg.x0_seed_base + k).T
     t0 = time.perf_counter()
-    r = olob.lobpcg(el, x0, J, tol=1e-30, max_iter=cpu_iters)
+    r = olob.lobpcg(el, x0, J, tol=tol)
+    oalb.make_alb(el, r.X, J)
     dt = time.perf_counter() - t0
-    per_iter = dt / max(1, r.iters)
-    est = per_iter * n_iters_scale
-    return {"value": round(1.0 / est, 5), "unit": "element-solves/s", "cores": n_workers(),
-            "kind": "oracle",
-            "sample": (f"element 5 of {cfg.n_elem}: {r.iters} oracle LOBPCG iterations in {dt:.1f} s "
-                       f"({per_iter:.2f} s/iteration), scaled to the {n_iters_scale} iterations the "
-                       f"GPU needed for that element to reach 1e-8 (ALB SVD time negligible)")}
+    return {"value": round(1.0 / dt, 5), "unit": "element-solves/s", "cores": n_workers(), "kind": "oracle",
+            "sample": (f"element {k} of {cfg.n_elem} (median cost; grid {'x'.join(map(str, el.n))}, J = {J}): "
+                       f"full oracle LOBPCG solve to {tol:g} ({r.iters} iterations, converged={r.converged}) "
+                       f"+ ALB SVD in {dt:.1f} s")}
 
 
 def make_x0(cfg, E, D, torch):
@@ -178,6 +207,7 @@ def main():
               "the element batch would shard across GPUs by whole elements with no communication, "
               "which is not measured here.", file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
     import torch
     import workloads as W
     from paper_2003_00407_amd import dgalb as D
@@ -194,61 +224,97 @@ def main():
         buf2.copy_(buf)
         del buf, buf2
     torch.cuda.synchronize()
-    print(f"[bench] config={cfg.name} elements={len(els)} grid={els[0].n} J={els[0].n_states}",
-          file=sys.stderr, flush=True)
-    meth = D.DG_LOBPCG if args.method == "lobpcg" else D.DG_CHFSI
-    r64 = run_path(E, x0, D.DG_FP64, args.steps, args.warmup, args.tol, torch, args.graph_iters, meth,
-                   args.cheb_degree)
-    print(f"[bench] fp64: {r64['seconds']:.3f}s for {args.steps} steps, iters {[int(i) for i in r64['iters']]}",
-          file=sys.stderr, flush=True)
     n = len(els)
-    value = n * args.steps / r64["seconds"]
+    grids = sorted({e.n for e in els})
+    js = [e.n_states for e in els]
+    log(f"config={cfg.name} elements={n} grids={grids} J={min(js)}..{max(js)} "
+        f"(setup {time.perf_counter() - t_start:.1f} s)")
+    meth = D.DG_LOBPCG if args.method == "lobpcg" else D.DG_CHFSI
+    kw64 = dict(precision=D.DG_FP64, tol=args.tol, graph_iters=args.graph_iters, method=meth,
+                cheb_degree=args.cheb_degree)
+    r64 = run_timed(E, x0, kw64, args.steps, args.warmup, args.tol, torch, "fp64")
+    step_s = r64["seconds"] / args.steps
+    log(f"fp64: {r64['seconds']:.3f} s for {args.steps} steps")
+    groups = int(os.environ.get("DG_STREAMS", "0")) or max(1, min(4, n // 4))
     out = {
-        "metric": "ALB element-solves/s + Hψ GB/s, mixed vs FP64 on one GPU at 1e-8 Ha eigen error",
-        "value": round(value, 4),
+        "metric": METRIC,
+        "value": round(n * args.steps / r64["seconds"], 4),
         "unit": "element-solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * r64["seconds"] / args.steps, 3),
+        "ms_per_step": round(1000.0 * step_s, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg.name + ": " + cfg.description, "n_elem": n,
-                   "grid": list(els[0].n), "states": els[0].n_states,
-                   "tol": args.tol, "method": args.method, "precision": "fp64", "graph_iters": args.graph_iters,
-                   "element_groups": int(os.environ.get("DG_STREAMS", "0")) or max(1, min(4, n // 4))},
-        "hpsi_GBs_fp64": hpsi_rate(r64),
-        "iters_fp64": [int(i) for i in r64["iters"]],
+                   "grids": [list(g) for g in grids], "states": [min(js), max(js)], "tol": args.tol,
+                   "method": args.method, "precision": "fp64", "graph_iters": args.graph_iters,
+                   "element_groups": groups},
+        "iters_fp64": {"min": int(np.min(r64["iters"])), "max": int(np.max(r64["iters"])),
+                       "mean": round(float(np.mean(r64["iters"])), 2)},
         "max_resid_fp64": r64["max_resid"],
-        "kernels_fp64": kernel_table(r64),
-        "roofline": roofline_for(r64, cfg.name),
+        "timing_note": "value: per-kernel event timing off; kernel tables from separate instrumented steps",
     }
+    skipped = []
+
+    def have_time(est_s):
+        return time.perf_counter() - t_start + est_s <= args.budget_s
+
     if not args.no_mixed:
-        rmx = run_path(E, x0, D.DG_MIXED, args.steps, args.warmup, args.tol, torch, args.graph_iters, meth,
-                       args.cheb_degree)
-        print(f"[bench] mixed: {rmx['seconds']:.3f}s", file=sys.stderr, flush=True)
-        out["mixed"] = {"value": round(n * args.steps / rmx["seconds"], 4),
-                        "ms_per_step": round(1000.0 * rmx["seconds"] / args.steps, 3),
-                        "speedup_vs_fp64": round(r64["seconds"] / rmx["seconds"], 3),
-                        "iters": [int(i) for i in rmx["iters"]], "max_resid": rmx["max_resid"],
-                        "kernels": kernel_table(rmx)}
+        kwmx = dict(kw64, precision=D.DG_MIXED)
+        if have_time((args.mixed_steps + 1) * step_s * 1.1):
+            rmx = run_timed(E, x0, kwmx, args.mixed_steps, 1, args.tol, torch, "mixed")
+            log(f"mixed: {rmx['seconds']:.3f} s for {args.mixed_steps} steps")
+            mx_step = rmx["seconds"] / args.mixed_steps
+            out["mixed"] = {"value": round(n / mx_step, 4), "steps": args.mixed_steps, "warmup": 1,
+                            "ms_per_step": round(1000.0 * mx_step, 3),
+                            "speedup_vs_fp64": round(step_s / mx_step, 3),
+                            "iters": {"min": int(np.min(rmx["iters"])), "max": int(np.max(rmx["iters"])),
+                                      "mean": round(float(np.mean(rmx["iters"])), 2)},
+                            "max_resid": rmx["max_resid"]}
+        else:
+            skipped.append("mixed")
+    if not args.no_instrumented and have_time(step_s * 1.3):
+        ri = run_instrumented(E, x0, kw64, args.tol, torch, "fp64 instrumented")
+        log(f"fp64 instrumented step: {ri['seconds']:.3f} s")
+        alg, passes = hpsi_rates(ri)
+        out["hpsi_GBs_fp64"] = alg
+        out["hpsi_pass_GBs_fp64"] = passes
+        out["kernels_fp64"] = kernel_table(ri)
+        out["roofline"] = roofline_for(ri, cfg.name)
+        out["roofline"]["measured"] = "instrumented FP64 step, element groups sharing the GPU"
+        if "mixed" in out and have_time(step_s * 1.2):
+            rim = run_instrumented(E, x0, dict(kw64, precision=D.DG_MIXED), args.tol, torch, "mixed instrumented")
+            alg, passes = hpsi_rates(rim)
+            out["mixed"]["hpsi_GBs"] = alg
+            out["mixed"]["kernels"] = kernel_table(rim)
+    elif not args.no_instrumented:
+        skipped.append("instrumented")
     if not args.no_isolated:
-        # all elements in one stream: kernel durations without overlap between element groups
-        del E
-        E1 = D.Elements(els, n_streams=1)
-        r1 = run_path(E1, x0, D.DG_FP64, 1, 0, args.tol, torch)
-        print(f"[bench] one stream: {r1['seconds']:.3f}s", file=sys.stderr, flush=True)
-        # kernels without overlap between groups: the dominant class's roofline here is
-        # the per-kernel figure (in the timed region launches of four groups share the GPU)
-        out["one_stream_fp64"] = {"value": round(n / r1["seconds"], 4), "hpsi_GBs": hpsi_rate(r1),
-                                  "kernels": kernel_table(r1),
-                                  "roofline": roofline_for(r1, cfg.name, with_traffic=False)}
+        if have_time(step_s * 2.5):
+            # all elements in one stream: kernel durations without overlap between groups
+            del E
+            torch.cuda.empty_cache()
+            E1 = D.Elements(els, n_streams=1)
+            one_step(E1, x0, kw64, args.tol, "one-stream warm-up")
+            r1 = run_instrumented(E1, x0, kw64, args.tol, torch, "one-stream")
+            log(f"one stream: {r1['seconds']:.3f} s")
+            alg, passes = hpsi_rates(r1)
+            out["one_stream_fp64"] = {"value": round(n / r1["seconds"], 4), "hpsi_GBs": alg,
+                                      "hpsi_pass_GBs": passes, "kernels": kernel_table(r1),
+                                      "roofline": roofline_for(r1, cfg.name, with_traffic=False)}
+            del E1
+        else:
+            skipped.append("one_stream")
     if not args.no_cpu_baseline:
-        print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, int(r64["iters"][5]), args.cpu_iters)
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.tol)
+    if skipped:
+        out["skipped_for_time"] = skipped
+    log(f"total {time.perf_counter() - t_start:.1f} s")
     print(json.dumps(out), flush=True)
 
 

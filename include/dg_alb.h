@@ -115,11 +115,21 @@ typedef struct {
   int32_t max_iter;    /* iteration cap per stage                                     */
   int32_t cheb_degree; /* DG_CHFSI filter degree m                                    */
   const double *x0_dev;/* packed initial blocks, N_k x (J_k + guards) per element     */
-                       /* (dg_query_offsets(DG_OFF_X0)); need not be orthonormal      */
+                       /* (dg_query_offsets(DG_OFF_X0)); need not be orthonormal.     */
+                       /* NULL: a seeded Gaussian start drawn on the device from      */
+                       /* seed (counter-based, so one seed gives one start for every  */
+                       /* element, independent of the element groups)                 */
   int32_t graph_iters; /* FP64 LOBPCG: > 0 captures this many iterations of every     */
                        /* element group as one HIP graph, replayed with one host      */
                        /* convergence check per replay (the count may then overshoot */
                        /* max_iter by less than graph_iters); 0: launch per kernel     */
+  int64_t seed;        /* seed of the device-drawn start (x0_dev == NULL)             */
+  int32_t warm_start;  /* nonzero: start from the eigenvectors and guard vectors of   */
+                       /* the last solve on this context (x0_dev and seed ignored),   */
+                       /* e.g. after dg_set_potential in an inner SCF step, where the */
+                       /* ALBs adapt to the updated V_eff; DG_ERR_STATE if no solve   */
+                       /* has left vectors on the context since the last band-energy */
+                       /* call                                                        */
 } dg_solve_params;
 
 enum dg_offset_kind {
@@ -159,22 +169,38 @@ void dg_destroy(dg_ctx *ctx);
 int32_t dg_query_offsets(const dg_ctx *ctx, int32_t kind, int64_t *offsets);
 
 /* y = H^{Q_k} x (Eq. (1)) for n_vec vectors per element: kinetic term by line
- * FFTs, local potential, nonlocal projectors.  elem = -1 applies every element
- * (x_dev, y_dev packed N_k x n_vec per element, concatenated); elem >= 0 applies
- * element elem only (x_dev, y_dev are N_elem x n_vec).  prec = DG_FP64: double
- * buffers; DG_FP32: float buffers.  x and y must not overlap.  n_vec must not
- * exceed J_k + g_k of any element applied.  Errors: DG_ERR_ARG, DG_ERR_HIP. */
+ * FFTs, local potential, nonlocal projectors.  elem = -1 applies every element,
+ * elem >= 0 element elem only.  Layout of x_dev (and likewise y_dev with ldy):
+ * ldx == 0: packed, N_k x n_vec column-major per element (leading dimension
+ * N_k), the elements' blocks concatenated (for elem >= 0 the one block);
+ * ldx > 0: every element's block is ldx x n_vec column-major (ldx >= N_k of
+ * every element applied), element blocks ldx * n_vec values apart (elem >= 0:
+ * the one block at x_dev).  prec = DG_FP64: double buffers; DG_FP32: float
+ * buffers.  x and y must not overlap.  n_vec must not exceed J_k + g_k of any
+ * element applied.  Errors: DG_ERR_ARG (NULL, ranges, ld too small), DG_ERR_HIP. */
 int32_t dg_apply_H(dg_ctx *ctx, int32_t elem, int32_t n_vec, int32_t prec,
-                   const void *x_dev, void *y_dev);
+                   const void *x_dev, int64_t ldx, void *y_dev, int64_t ldy);
 
 /* Lowest J_k eigenpairs of every H^{Q_k} ("Generating ALB functions";
  * Algorithm 1 or 2).  eig_dev, resid_dev: J_k FP64 values per element
  * (DG_OFF_EIG); iters_host: n_elem iteration counts (may be NULL).  The
- * eigenvectors stay in the context for dg_make_alb / dg_get_vectors.
- * Returns DG_WARN_NOT_CONVERGED when some element missed tol after max_iter.
- * Errors: DG_ERR_ARG, DG_ERR_NUMERIC, DG_ERR_HIP. */
+ * eigenvectors stay in the context for dg_make_alb / dg_get_vectors and for a
+ * warm-started solve.  Returns DG_WARN_NOT_CONVERGED when some element missed
+ * tol after max_iter.  Errors: DG_ERR_ARG; DG_ERR_STATE (warm_start without
+ * vectors); DG_ERR_NUMERIC: a non-finite residual (NaN/Inf in V_eff or the
+ * start), a rank-deficient start block (the Cholesky of X_0^T X_0 breaks
+ * down, e.g. repeated columns), or an element that did not converge after a
+ * Rayleigh-Ritz breakdown of its X block; DG_ERR_HIP. */
 int32_t dg_solve_elements(dg_ctx *ctx, const dg_solve_params *params, double *eig_dev,
                           double *resid_dev, int32_t *iters_host);
+
+/* All J_k + g_k Ritz values of the last solve (the J_k wanted states, then the
+ * guard states) and their residual norms, FP64, packed per element
+ * (DG_OFF_KALL).  The guards bound the gap lambda_{J+1} - lambda_J that
+ * conditions the ALB subspace: theta_{J+1} - theta_J near zero means the cut at
+ * J_k splits a (nearly) degenerate cluster and the ALB span is not unique.
+ * Errors: DG_ERR_STATE before a solve, DG_ERR_ARG. */
+int32_t dg_get_ritz(dg_ctx *ctx, double *theta_dev, double *resid_dev);
 
 /* Copy the converged eigenvectors (first J_k columns, FP64) to x_dev, packed
  * N_k x J_k per element (DG_OFF_VEC).  Errors: DG_ERR_STATE before a solve. */
@@ -185,7 +211,9 @@ int32_t dg_get_vectors(dg_ctx *ctx, double *x_dev);
  * alb_dev: packed |E_k| x J_k FP64 (DG_OFF_ALB), columns orthonormal, spanning
  * the restricted eigenvectors; sval_dev: J_k singular values of the
  * restriction, descending (DG_OFF_EIG).  Errors: DG_ERR_STATE before a solve,
- * DG_ERR_NUMERIC if the restriction is rank deficient. */
+ * DG_ERR_NUMERIC if the restriction is rank deficient for some element
+ * (sigma_min <= 1e-10 sigma_max, or the orthonormalisation breaks down): the
+ * outputs are then not valid. */
 int32_t dg_make_alb(dg_ctx *ctx, double *alb_dev, double *sval_dev);
 
 /* Band energy E = sum_i f_i psi_i^T H psi_i with Psi = p_m(H) Psi_0, p_m the
@@ -214,8 +242,22 @@ int32_t dg_band_energy_backward(dg_ctx *ctx, const double *dE_host, void *dpsi0_
 /* Replace V_eff of every element (v_dev: FP64 device buffer, packed N_k per
  * element, DG_OFF_GRID), e.g. for an inner SCF step ("Generating ALB
  * functions": the ALBs adapt as V_eff changes) or for finite differences in V.
- * Invalidates previous eigenvectors.  Errors: DG_ERR_ARG. */
+ * The spectral upper bound used by the Chebyshev filter is recomputed from the
+ * new maximum of V_eff.  The eigenvectors of the last solve are kept as a
+ * warm start (dg_solve_params.warm_start) but no longer count as a solution:
+ * dg_make_alb and dg_get_vectors need a new solve.  A pending band energy is
+ * invalidated (its backward returns DG_ERR_STATE).  Errors: DG_ERR_ARG. */
 int32_t dg_set_potential(dg_ctx *ctx, const double *v_dev);
+
+/* Algorithmic work of the launches timed since the last reset (9 values):
+ * [0..7] per class of dg_timing: bytes for classes 0-3 (each pass's own minimal
+ * reads and writes), flops for classes 4-5 (2 r n_i n_j per product, r n (n+1)
+ * for a symmetric n x n Gram), 0 for 6-7; [8] the bytes of the H*psi state
+ * applications (classes 0-2 together) by the per-state count 2 N s + N s / J +
+ * nnz (s + 4) / J (read psi, write H psi, V and the projectors amortised over
+ * the J wanted states; s = 8 or 4 bytes).  Call before a resetting dg_timing.
+ * Errors: DG_ERR_ARG. */
+int32_t dg_timing_work(dg_ctx *ctx, double *work_host);
 
 /* Per-kernel-class GPU time accumulated since the last reset, measured with
  * HIP events recorded on the context's stream around each launch group.
@@ -225,12 +267,6 @@ int32_t dg_set_potential(dg_ctx *ctx, const double *v_dev);
  * 7 other.  ms_host[8], launches_host[8] (may be NULL) receive the totals,
  * then reset != 0 clears them and enable sets timing on or off (default off).
  * Synchronises the stream.  Errors: DG_ERR_ARG, DG_ERR_HIP. */
-/* Algorithmic work of the launches timed since the last reset, per class of
- * dg_timing (8 values): bytes for classes 0-3 (each pass's own minimal reads
- * and writes), flops for classes 4-5, 0 for 6-7.  Call before a resetting
- * dg_timing.  Errors: DG_ERR_ARG. */
-int32_t dg_timing_work(dg_ctx *ctx, double *work_host);
-
 int32_t dg_timing(dg_ctx *ctx, int32_t enable, int32_t reset, double *ms_host,
                   int64_t *launches_host);
 

@@ -264,6 +264,7 @@ int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* 
                       (void*)b->own[i]);
       if (st < 0) return st;
       worst = std::max(worst, st);
+      c->elem_base = b->lo[i];
       b->g.push_back(std::move(*c));
       delete c;
       used += round256(need);
@@ -300,8 +301,8 @@ int32_t dg_query_offsets(const dg_ctx* ctx, int32_t kind, int64_t* offsets) {
   return DG_OK;
 }
 
-int32_t dg_apply_H(dg_ctx* ctx, int32_t elem, int32_t n_vec, int32_t prec, const void* x_dev,
-                   void* y_dev) {
+int32_t dg_apply_H(dg_ctx* ctx, int32_t elem, int32_t n_vec, int32_t prec, const void* x_dev, int64_t ldx,
+                   void* y_dev, int64_t ldy) {
   if (!ctx) {
     dg::set_error("ctx is NULL");
     return DG_ERR_ARG;
@@ -312,16 +313,23 @@ int32_t dg_apply_H(dg_ctx* ctx, int32_t elem, int32_t n_vec, int32_t prec, const
       dg::set_error("elem out of range");
       return DG_ERR_ARG;
     }
+    if (ldx < 0 || ldy < 0) {
+      dg::set_error("ldx and ldy must be >= 0");
+      return DG_ERR_ARG;
+    }
     const size_t sz = prec == DG_FP32 ? sizeof(float) : sizeof(double);
     if (int st = ctx->fork()) return st;
     int st = each_group(ctx, [&](int i) {
       const int a = ctx->lo[i], z = ctx->lo[i + 1];
       if (elem >= 0) {
         if (elem < a || elem >= z) return (int)DG_OK;
-        return dg::apply_h(ctx->g[i], elem - a, n_vec, prec, x_dev, y_dev);
+        return dg::apply_h(ctx->g[i], elem - a, n_vec, prec, x_dev, ldx, y_dev, ldy);
       }
-      const int64_t o = ctx->off[DG_OFF_GRID][a] * (int64_t)std::max(n_vec, 0);
-      return dg::apply_h(ctx->g[i], -1, n_vec, prec, shift(x_dev, o, sz), shift(y_dev, o, sz));
+      // this group's first element block: packed offsets, or a elements of ld * n_vec
+      const int64_t nv = std::max(n_vec, 0);
+      const int64_t ox = ldx > 0 ? (int64_t)a * ldx * nv : ctx->off[DG_OFF_GRID][a] * nv;
+      const int64_t oy = ldy > 0 ? (int64_t)a * ldy * nv : ctx->off[DG_OFF_GRID][a] * nv;
+      return dg::apply_h(ctx->g[i], -1, n_vec, prec, shift(x_dev, ox, sz), ldx, shift(y_dev, oy, sz), ldy);
     });
     if (st < 0) return st;
     if (int s2 = ctx->join()) return s2;
@@ -344,6 +352,23 @@ int32_t dg_solve_elements(dg_ctx* ctx, const dg_solve_params* params, double* ei
       return dg::solve(ctx->g[i], &p, shift(eig_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)),
                        shift(resid_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)),
                        iters_host ? iters_host + a : nullptr);
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
+}
+
+int32_t dg_get_ritz(dg_ctx* ctx, double* theta_dev, double* resid_dev) {
+  if (!ctx) {
+    dg::set_error("ctx is NULL");
+    return DG_ERR_ARG;
+  }
+  DG_GUARD({
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int64_t o = ctx->off[DG_OFF_KALL][ctx->lo[i]];
+      return dg::get_ritz(ctx->g[i], shift(theta_dev, o, sizeof(double)), shift(resid_dev, o, sizeof(double)));
     });
     if (st < 0) return st;
     if (int s2 = ctx->join()) return s2;
@@ -454,6 +479,8 @@ int32_t dg_timing_work(dg_ctx* ctx, double* work_host) {
     work_host[i] = 0.0;
     for (const Ctx& c : ctx->g) work_host[i] += c.tacc.work[i];
   }
+  work_host[dg::TC_N] = 0.0;
+  for (const Ctx& c : ctx->g) work_host[dg::TC_N] += c.tacc.hpsi_alg;
   return DG_OK;
 }
 

@@ -53,6 +53,7 @@ int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters
   DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   c.active_host.assign(c.n_elem, 1);
   c.rr_pivot_tol = (prec == DG_FP64) ? 1e-13 : 1e-6;
+  DG_HIP(hipMemsetAsync(c.dev_count + 2, 0, sizeof(int), c.stream));
   const std::vector<int> pool = {B_W, B_P, B_HW, B_HP, B_T0, B_T1};
   // start: Rayleigh-Ritz on span(X0) gives the first Ritz values (lower bounds)
   auto rr_into_x = [&](int y, int hy) -> int {
@@ -87,10 +88,15 @@ int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters
   for (it = 1; it <= max_iter; ++it) {
     if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
     if ((st = launch_check(c, active, tol))) return st;
-    int cnt[2];
+    int cnt[4];
     if ((st = sync_read_c(c, cnt, c.dev_count, sizeof(cnt)))) return st;
     if (cnt[1] > 0) {
       set_error("non-finite residual");
+      return DG_ERR_NUMERIC;
+    }
+    if (it == 1 && cnt[2] > 0) {
+      set_error("the start block is rank deficient in " + std::to_string(cnt[2]) +
+                " element(s): the Cholesky factorisation of X0^T X0 broke down");
       return DG_ERR_NUMERIC;
     }
     std::vector<int> act(c.n_elem);
@@ -124,12 +130,17 @@ int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters
   DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
   if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
   if ((st = launch_check(c, active, tol))) return st;
-  int cnt[2];
+  int cnt[4];
   if ((st = sync_read_c(c, cnt, c.dev_count, sizeof(cnt)))) return st;
   if (iters)
     for (int e = 0; e < c.n_elem; ++e) iters[e] = it_elem[e];
   *n_done = c.n_elem - cnt[0];
-  return cnt[1] > 0 ? DG_ERR_NUMERIC : DG_OK;
+  c.last_breakdowns = cnt[2];
+  if (cnt[1] > 0) {
+    set_error("non-finite residual");
+    return DG_ERR_NUMERIC;
+  }
+  return DG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -199,6 +210,7 @@ int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_v
   if ((st = launch_weighted_dot(c, prec, L.ym(), L.hym(), n_vec, f, 1.0, E))) return st;
   c.be_valid = true;
   c.solved = false;   // the solver blocks now hold filter iterates
+  c.have_x = false;
   c.be_degree = degree;
   c.be_prec = prec;
   c.be_nvec = n_vec;
@@ -248,7 +260,9 @@ int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv) {
       a1 = t;
     }
   }
-  // dE/dPsi_0 = A_0 (packed like psi0)
+  // dE/dPsi_0 = A_0 (packed like psi0); the solver blocks hold adjoint iterates now
+  c.solved = false;
+  c.have_x = false;
   if ((st = launch_copy_ext(c, prec, a1, dpsi0, -1, n_vec, 1))) return st;
   DG_HIP(hipStreamSynchronize(c.stream));
   return DG_OK;

@@ -48,6 +48,7 @@ struct ElemDev {
   // blocks kMaxBlocks.. exist only when the context was created for band energies
   void* blk[kTotalBlocks];
   double bup;              // upper bound of the spectrum of H^{Q_k} (Chebyshev filter)
+  double bup_base;         // its V-independent part: kinetic maximum + nonlocal Gershgorin bound
   // per-element small-matrix workspace (FP64)
   double* small;           // see SmallLayout
   double* nlc;             // projector overlaps C = B^T X: nproj x Kmax3 (FP64)
@@ -85,6 +86,7 @@ struct TimingAcc {
   double ms[TC_N] = {0};
   int64_t launches[TC_N] = {0};
   double work[TC_N] = {0};   // algorithmic bytes (passes 0-3) or flops (4-5) of the timed launches
+  double hpsi_alg = 0;       // H*psi bytes by the per-state formula 2Ns + Ns/J + nnz(s+4)/J
 };
 
 struct PendingTime {
@@ -103,7 +105,10 @@ struct Ctx {
   std::vector<int64_t> off_x0, off_vec, off_eig, off_alb, off_grid, off_kall;
   char* arena = nullptr;
   size_t arena_bytes = 0, arena_used = 0;
-  bool solved = false;
+  bool solved = false;             // the blocks hold a solution (ALBs, vectors may be taken)
+  bool have_x = false;             // X (with guards) of the last solve is intact: warm start possible
+  int elem_base = 0;               // index of this group's first element in the whole batch
+  int last_breakdowns = 0;         // Rayleigh-Ritz breakdowns of the X block in the last stage
   int solved_K3 = 0;
   // band-energy state
   int be_degree = 0, be_prec = 0, be_nvec = 0, be_stride = 1, be_nckpt = 0;
@@ -125,7 +130,7 @@ struct Ctx {
   int* iota_dev = nullptr;         // 0..n_elem-1
   int* dev_active = nullptr;       // per element solver flags
   int* dev_status = nullptr;       // per element RR status
-  int* dev_count = nullptr;        // [active count, NaN count]
+  int* dev_count = nullptr;        // [active count, NaN count, Rayleigh-Ritz breakdowns, -]
   int* dev_iters = nullptr;        // per element iterations performed (counted by the check kernel)
   bool capturing = false;          // a stream capture is open: no timing events
   double* dev_maxres = nullptr;    // per element max residual
@@ -139,6 +144,7 @@ struct Ctx {
   long long* dev_off_alb = nullptr;
   long long* dev_off_grid = nullptr;
   long long* dev_off_eig = nullptr;
+  long long* dev_off_kall = nullptr;
   std::vector<int> host_ints;      // staging for small async uploads
   std::vector<int> host_ints2;      // staging of the iteration-counter reset
   std::vector<int> active_host;    // host mirror of the solver's active flags (work accounting)
@@ -226,7 +232,16 @@ int launch_gram_rows(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
 // where the shapes allow it, else as two Grams
 int launch_gram_pair(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT, long long out_off_st,
                      long long out_off_ss, const int* active);
-int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed);
+// caller buffer <-> block: ld == 0 packed (N_k per element), ld > 0 every element's
+// block ld x ncol, element blocks ld * ncol apart
+int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed,
+                    long long ld = 0);
+// seeded Gaussian start block (counter-based: element index + elem_base, column, row)
+int launch_random_block(Ctx& c, int prec, int blk, unsigned long long seed);
+// per element: bup = bup_base + max(max V, 0) (after a potential update)
+int launch_update_bounds(Ctx& c);
+// J+g Ritz values and residuals per element into packed outputs (DG_OFF_KALL)
+int launch_extract_kall(Ctx& c, double* theta, double* resid);
 int launch_copy_packed(Ctx& c, int prec, int blk, const double* ptr, const long long* off, int ncol,
                        int to_packed);
 int launch_gather_e(Ctx& c, int src_blk, int dst_blk);
@@ -240,7 +255,7 @@ int launch_permute(Ctx& c, const int* perm, const int* active);
 int query_workspace(int n_elem, const dg_element_desc* d, const dg_options* opt, size_t* bytes);
 int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* opt, void* arena,
            size_t arena_bytes, void* stream);
-int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y);
+int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, long long ldx, void* y, long long ldy);
 int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters);
 int get_vectors(Ctx& c, double* x);
 int make_alb(Ctx& c, double* alb, double* sval);
@@ -248,5 +263,6 @@ int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_v
                 const double* f, double* E);
 int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv);
 int set_potential(Ctx& c, const double* v);
+int get_ritz(Ctx& c, double* theta, double* resid);
 
 }  // namespace dg

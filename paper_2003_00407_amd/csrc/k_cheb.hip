@@ -209,6 +209,34 @@ __global__ void __launch_bounds__(256) k_set_potential(const ElemDev* elems, con
   const_cast<float*>(E.v32)[r] = float(x);
 }
 
+// spectral upper bound after a potential update: bup = bup_base + max(max V, 0),
+// a NaN in V propagates into bup (fmax would drop it)
+__global__ void __launch_bounds__(1024) k_update_bounds(ElemDev* elems) {
+  const int e = blockIdx.x;
+  ElemDev& E = elems[e];
+  double m = -1e300;
+  bool nan = false;
+  for (int r = threadIdx.x; r < E.N; r += 1024) {
+    const double x = E.v64[r];
+    nan |= !(x == x);
+    m = fmax(m, x);
+  }
+  __shared__ double sh[16];
+  __shared__ int snan;
+  if (threadIdx.x == 0) snan = 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  if (nan) atomicOr(&snan, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = sh[0];
+    for (int w = 1; w < 16; ++w) mm = fmax(mm, sh[w]);
+    E.bup = snan ? __builtin_nan("") : E.bup_base + fmax(mm, 0.0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -296,7 +324,18 @@ int set_potential(Ctx& c, const double* v) {
   dim3 g((maxN(c) + 255) / 256, c.n_elem);
   hipLaunchKernelGGL(k_set_potential, g, dim3(256), 0, c.stream, c.elems_dev, v, c.dev_off_grid);
   DG_HIP(hipGetLastError());
+  int st;
+  if ((st = launch_update_bounds(c))) return st;
+  // the eigenvectors stay as a warm start, but are no solution of the new H
   c.solved = false;
+  // a band energy taken at the old potential can no longer be differentiated
+  c.be_valid = false;
+  return DG_OK;
+}
+
+int launch_update_bounds(Ctx& c) {
+  hipLaunchKernelGGL(k_update_bounds, dim3(c.n_elem), dim3(1024), 0, c.stream, c.elems_dev);
+  DG_HIP(hipGetLastError());
   return DG_OK;
 }
 

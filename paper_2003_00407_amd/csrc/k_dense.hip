@@ -6,8 +6,9 @@
 //    tiles, then a fixed-order reduction (deterministic).
 //  * Rayleigh-Ritz on the small projected problem, FP64, one workgroup per
 //    element: diagonal scaling, Cholesky S^T S = U^T U, U^{-1}, the standard
-//    problem U^{-T} A U^{-1}, cyclic Jacobi with a parallel (round-robin)
-//    ordering, then the coefficients C = D U^{-1} V of the lowest eigenpairs.
+//    problem U^{-T} A U^{-1}, Householder tridiagonalisation, Sturm
+//    multisection and inverse iteration, then the coefficients C = D U^{-1} V
+//    of the lowest eigenpairs.
 //  * Rotations X <- S C (Eq. (2), Algorithm 1 steps 6-7; Algorithm 2 step 5).
 //  * Residual norms ||H x_i - theta_i x_i|| and the preconditioner energy.
 #include "dg_internal.h"
@@ -50,12 +51,16 @@ __device__ __forceinline__ const T* vcol(const ElemDev& E, const ColSet& s, int 
 // ---------------------------------------------------------------------------
 // Gram: part[e][split][i][j] = sum_{r in split} S[r,i] T[r,j]
 //
-// Row-panel design: a workgroup owns one element and one contiguous range of
-// grid rows, stages GP_R rows of EVERY column of S (and of T unless T == S)
-// in LDS per step, and accumulates the whole output (or the upper triangle,
-// for a symmetric result) in MFMA registers. Each input value is read from
-// HBM once per Gram; the partial sums of the row ranges are reduced in a
-// fixed order afterwards (deterministic).
+// Tiled row-panel design.  The 16x16 output blocks form a grid (bi x bj, the
+// upper triangle when the result is symmetric); it is cut into square tiles of
+// tb x tb blocks.  A workgroup owns one element, one tile and one contiguous
+// range of grid rows: per step it stages GP_R rows of only the columns its tile
+// touches (S columns of the tile's block rows, T columns of its block columns)
+// in LDS and accumulates the tile's blocks in MFMA registers.  In pair mode a
+// tile also holds the same blocks of S^T S, whose columns are S's (staged once
+// on the diagonal).  With tb >= bi there is one tile: every column is staged
+// once and read from HBM once per Gram.  Partial sums of the row ranges are
+// reduced in a fixed order afterwards (deterministic).
 // ---------------------------------------------------------------------------
 struct GramArgs {
   const ElemDev* elems;
@@ -65,8 +70,10 @@ struct GramArgs {
   int nsplit;
   int rows_e;          // 1: reduce over the first |E_k| rows only
   int sym;             // 1: the result is symmetric, only 16x16 blocks with p <= q are computed
-  int same;            // 1: T is the same column set as S (staged once)
-  int cap;             // output blocks per workgroup (8 waves x MAXB)
+  int same;            // 1: T is the same column set as S
+  int tb;              // tile side in 16x16 blocks
+  int ntile;           // tiles of the largest element (work items per row range)
+  int n_elem;          // elements in the launch
   double* part;        // per element region of part_stride doubles
   long long part_stride;
   int part_ld;         // leading dim of a partial matrix
@@ -76,8 +83,7 @@ struct GramArgs {
 
 constexpr int GP_THREADS = 512;
 constexpr int GP_R = 16;        // grid rows staged per step
-constexpr int GP_MAXCOL = 576;  // staged columns (S and T, padded to 16) per workgroup
-constexpr int GP_PF = GP_MAXCOL / (GP_THREADS / GP_R);   // staged values per thread and step
+constexpr int GP_MAXCOL = 384;  // staged columns per workgroup (tiles are chosen to fit)
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
@@ -88,7 +94,7 @@ __device__ __forceinline__ d4v mfma16x16x4(double a, double b, d4v c) {
 }
 
 // 16x16 output block number b -> (p, q): row-major over p <= q when sym, else over all
-__device__ __forceinline__ void gram_block(int b, int bi, int bj, int sym, int& p, int& q) {
+__host__ __device__ __forceinline__ void gram_block(int b, int bi, int bj, int sym, int& p, int& q) {
   if (!sym) {
     p = b / bj;
     q = b - p * bj;
@@ -102,55 +108,140 @@ __device__ __forceinline__ void gram_block(int b, int bi, int bj, int sym, int& 
   q = p + b;
 }
 
+// One tile of a Gram launch, for an element with bi x bj output blocks.
+struct GramTile {
+  int P0, P1, Q0, Q1;   // block rows / columns
+  bool diag;            // symmetric result, tile on the diagonal: blocks p <= q only
+  int ncA, ncB, ncC;    // staged columns: S rows-range, T cols-range, S cols-range (pair, off-diagonal)
+  int nloc;             // blocks per product
+};
+
+__host__ __device__ __forceinline__ int gram_ntiles(int bi, int bj, int tb, int sym) {
+  const int ti = (bi + tb - 1) / tb, tj = (bj + tb - 1) / tb;
+  return sym ? ti * (ti + 1) / 2 : ti * tj;
+}
+
+__host__ __device__ __forceinline__ GramTile gram_tile(int tile, int bi, int bj, int tb, int sym, int same,
+                                                       int pair) {
+  const int ti = (bi + tb - 1) / tb, tj = (bj + tb - 1) / tb;
+  int I, J;
+  gram_block(tile, ti, tj, sym, I, J);
+  GramTile g;
+  g.P0 = I * tb;
+  g.P1 = min(bi, g.P0 + tb);
+  g.Q0 = J * tb;
+  g.Q1 = min(bj, g.Q0 + tb);
+  g.diag = sym && I == J;
+  const int np = g.P1 - g.P0, nq = g.Q1 - g.Q0;
+  g.ncA = 16 * np;
+  g.ncB = (same && g.diag) ? 0 : 16 * nq;
+  g.ncC = (pair && !g.diag) ? 16 * nq : 0;
+  g.nloc = g.diag ? np * (np + 1) / 2 : np * nq;
+  return g;
+}
+
+// Block b of a tile's list (blocks nloc .. 2 nloc - 1 are those of S^T S in pair
+// mode): LDS columns of its A and B operands, and its output position packed as
+// (row block << 16) | (column block << 1) | second product.
+__host__ __device__ __forceinline__ void gram_tile_block(const GramTile& g, int b, int offB, int offC, int& acol,
+                                                         int& bcol, int& pos) {
+  const int np = g.P1 - g.P0, nq = g.Q1 - g.Q0;
+  const int second = b >= g.nloc;
+  const int lb = b - second * g.nloc;
+  int dp, dq;
+  if (g.diag) {
+    gram_block(lb, np, np, 1, dp, dq);
+  } else {
+    dp = lb / nq;
+    dq = lb - dp * nq;
+  }
+  acol = dp * 16;
+  bcol = (second ? offC : offB) + dq * 16;
+  pos = ((g.P0 + dp) << 16) | ((g.Q0 + dq) << 1) | second;
+}
+
+// Work item of a Gram workgroup on the 1D grid (ntile x row ranges, the row ranges
+// padded to a multiple of 8).  Workgroup p is dispatched to XCD p % 8; its item is
+// chosen so that each XCD runs every tile of its row ranges (split, element) back
+// to back: the tiles of one row range stage overlapping columns, which that XCD's
+// L2 then serves, and the row ranges are interleaved over the XCDs for balance.
+struct GramItem {
+  int tile, split, e;
+  bool valid;
+};
+
+__device__ __forceinline__ GramItem gram_item(const GramArgs& A) {
+  const int p = blockIdx.x;
+  const int xcd = p & 7, slot = p >> 3;
+  const int tile = slot % A.ntile, j = slot / A.ntile;
+  const int rr = j * 8 + xcd;
+  GramItem it;
+  it.tile = tile;
+  it.split = rr % A.nsplit;
+  it.e = rr / A.nsplit;
+  it.valid = it.e < A.n_elem;
+  return it;
+}
+
 // PF: staged values per thread and step (32 columns per pass of the workgroup)
 template <typename T, int MAXB, int PF>
 __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
-  const int e = blockIdx.z;
+  const GramItem item = gram_item(A);
+  if (!item.valid) return;
+  const int e = item.e;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
   const int kS = kcode(A.kS, E);
   const int kT = kcode(A.kT, E);
   const int ni = A.S.nb * kS, nj = A.T.nb * kT;
   const int bi = (ni + 15) >> 4, bj = (nj + 15) >> 4;
-  const int nblk = A.sym ? bi * (bi + 1) / 2 : bi * bj;
-  const int nblk_all = A.pair ? 2 * nblk : nblk;
-  const int b0 = blockIdx.x * A.cap;
-  if (b0 >= nblk_all) return;
-  const int split = blockIdx.y;
+  if (item.tile >= gram_ntiles(bi, bj, A.tb, A.sym)) return;
+  const GramTile g = gram_tile(item.tile, bi, bj, A.tb, A.sym, A.same, A.pair);
+  const int nblk_all = A.pair ? 2 * g.nloc : g.nloc;
+  const int split = item.split;
   const int nrows = nrows_of(E, A.rows_e);
   const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GP_R - 1) / GP_R * GP_R;
   const int r0 = split * rows_per;
   const int r1 = min(nrows, r0 + rows_per);
-  const int ncS = bi * 16, nc = ncS + (A.same ? 0 : bj * 16);
-  const int toff = A.same ? 0 : ncS;      // LDS column of T's first column
+  const int nc = g.ncA + g.ncB + g.ncC;
+  // LDS column of the B operand's first staged column, per product
+  const int offB = (A.same && g.diag) ? 0 : g.ncA;
+  const int offC = g.diag ? 0 : g.ncA + g.ncB;
   const int pitch = nc + 1;
   extern __shared__ double gsm[];
   double* sm = gsm;                                       // [GP_R][pitch]
   const T** cp = reinterpret_cast<const T**>(gsm + GP_R * pitch);   // [nc]
   for (int c = threadIdx.x; c < nc; c += GP_THREADS) {
     const T* ptr = nullptr;
-    if (c < ncS) {
-      if (c < ni) ptr = vcol<T>(E, A.S, c, kS);
-    } else if (c - ncS < nj) {
-      ptr = vcol<T>(E, A.T, c - ncS, kT);
+    if (c < g.ncA) {
+      const int v = 16 * g.P0 + c;
+      if (v < ni) ptr = vcol<T>(E, A.S, v, kS);
+    } else if (c < g.ncA + g.ncB) {
+      const int v = 16 * g.Q0 + c - g.ncA;
+      if (A.same) {
+        if (v < ni) ptr = vcol<T>(E, A.S, v, kS);
+      } else if (v < nj) {
+        ptr = vcol<T>(E, A.T, v, kT);
+      }
+    } else {
+      const int v = 16 * g.Q0 + c - g.ncA - g.ncB;
+      if (v < ni) ptr = vcol<T>(E, A.S, v, kS);
     }
     cp[c] = ptr;
   }
   // the wave index is uniform: the block bookkeeping below stays in scalar registers
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // this wave's output blocks: b0 + w + 8 t; in pair mode blocks nblk .. 2 nblk - 1 are
-  // those of S^T S (B operand from the S columns)
-  int bp[MAXB], bq[MAXB];
+  // this wave's output blocks: w + 8 t of the tile's list (blocks nloc .. 2 nloc - 1
+  // are those of S^T S in pair mode); bp, bq: LDS columns of the A and B operands,
+  // bo: output position (row block, column block)
+  int bp[MAXB], bq[MAXB], bo[MAXB];
   bool bv[MAXB];
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
-    const int b = b0 + w + 8 * t;
-    bv[t] = b < nblk_all && b < b0 + A.cap;
-    const int second = b >= nblk;
-    int p = 0, q = 0;
-    if (bv[t]) gram_block(b - second * nblk, bi, bj, A.sym, p, q);
-    bp[t] = p * 16;
-    bq[t] = (second ? 0 : toff) + q * 16;
+    const int b = w + 8 * t;
+    bv[t] = b < nblk_all;
+    bp[t] = bq[t] = bo[t] = 0;
+    if (bv[t]) gram_tile_block(g, b, offB, offC, bp[t], bq[t], bo[t]);
   }
   const int l16 = lane & 15;
   d4v acc[MAXB];
@@ -195,9 +286,9 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
     if (!bv[t]) continue;
-    const bool second = b0 + w + 8 * t >= nblk;
+    const bool second = bo[t] & 1;
     double* o = second ? out + A.part_pair : out;
-    const int i0 = bp[t], j = bq[t] + l16 - (second ? 0 : toff);
+    const int i0 = (bo[t] >> 16) * 16, j = ((bo[t] >> 1) & 0x7FFF) * 16 + l16;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + (lane >> 4) + 4 * q;
@@ -231,46 +322,56 @@ __device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint
 // PF: staged values per thread and stage (16 columns per pass of the workgroup)
 template <int MAXB, int PF>
 __global__ void __launch_bounds__(GP_THREADS) k_gram_bf16(GramArgs A) {
-  const int e = blockIdx.z;
+  const GramItem item = gram_item(A);
+  if (!item.valid) return;
+  const int e = item.e;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
   const int kS = kcode(A.kS, E);
   const int kT = kcode(A.kT, E);
   const int ni = A.S.nb * kS, nj = A.T.nb * kT;
   const int bi = (ni + 15) >> 4, bj = (nj + 15) >> 4;
-  const int nblk = A.sym ? bi * (bi + 1) / 2 : bi * bj;
-  const int b0 = blockIdx.x * A.cap;
-  if (b0 >= nblk) return;
-  const int split = blockIdx.y;
+  if (item.tile >= gram_ntiles(bi, bj, A.tb, A.sym)) return;
+  const GramTile g = gram_tile(item.tile, bi, bj, A.tb, A.sym, A.same, A.pair);
+  const int nblk_all = A.pair ? 2 * g.nloc : g.nloc;
+  const int split = item.split;
   const int nrows = nrows_of(E, A.rows_e);
   const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + GB_R - 1) / GB_R * GB_R;
   const int r0 = split * rows_per;
   const int r1 = min(nrows, r0 + rows_per);
-  const int ncS = bi * 16, nc = ncS + (A.same ? 0 : bj * 16);
-  const int toff = A.same ? 0 : ncS;
+  const int nc = g.ncA + g.ncB + g.ncC;
+  const int offB = (A.same && g.diag) ? 0 : g.ncA;
+  const int offC = g.diag ? 0 : g.ncA + g.ncB;
   extern __shared__ double gsm[];
   unsigned short* sm = reinterpret_cast<unsigned short*>(gsm);          // [3][nc][GB_PITCH]
   const float** cp = reinterpret_cast<const float**>(sm + 3 * nc * GB_PITCH);   // [nc]
   for (int c = threadIdx.x; c < nc; c += GP_THREADS) {
     const float* ptr = nullptr;
-    if (c < ncS) {
-      if (c < ni) ptr = vcol<float>(E, A.S, c, kS);
-    } else if (c - ncS < nj) {
-      ptr = vcol<float>(E, A.T, c - ncS, kT);
+    if (c < g.ncA) {
+      const int v = 16 * g.P0 + c;
+      if (v < ni) ptr = vcol<float>(E, A.S, v, kS);
+    } else if (c < g.ncA + g.ncB) {
+      const int v = 16 * g.Q0 + c - g.ncA;
+      if (A.same) {
+        if (v < ni) ptr = vcol<float>(E, A.S, v, kS);
+      } else if (v < nj) {
+        ptr = vcol<float>(E, A.T, v, kT);
+      }
+    } else {
+      const int v = 16 * g.Q0 + c - g.ncA - g.ncB;
+      if (v < ni) ptr = vcol<float>(E, A.S, v, kS);
     }
     cp[c] = ptr;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int bp[MAXB], bq[MAXB];
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int bp[MAXB], bq[MAXB], bo[MAXB];
   bool bv[MAXB];
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
-    const int b = b0 + w + 8 * t;
-    bv[t] = b < nblk && b < b0 + A.cap;
-    int p = 0, q = 0;
-    if (bv[t]) gram_block(b, bi, bj, A.sym, p, q);
-    bp[t] = p;
-    bq[t] = q;
+    const int b = w + 8 * t;
+    bv[t] = b < nblk_all;
+    bp[t] = bq[t] = bo[t] = 0;
+    if (bv[t]) gram_tile_block(g, b, offB, offC, bp[t], bq[t], bo[t]);
   }
   double acc[MAXB][4];
 #pragma unroll
@@ -319,34 +420,36 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram_bf16(GramArgs A) {
 #pragma unroll
     for (int t = 0; t < MAXB; ++t) {
       if (!bv[t]) continue;
-      const int ca = (bp[t] * 16 + (lane & 15)) * GB_PITCH + koff;
-      const int cb = (toff + bq[t] * 16 + (lane & 15)) * GB_PITCH + koff;
+      const int ca = (bp[t] + (lane & 15)) * GB_PITCH + koff;
+      const int cb = (bq[t] + (lane & 15)) * GB_PITCH + koff;
       const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sm + ca);
       const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sm + plane + ca);
       const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(sm + 2 * plane + ca);
       const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(sm + cb);
       const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(sm + plane + cb);
       const bf16x8 c2 = *reinterpret_cast<const bf16x8*>(sm + 2 * plane + cb);
-      f4v s = {0.f, 0.f, 0.f, 0.f};
-      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, c1, s, 0, 0, 0);
-      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c2, s, 0, 0, 0);
-      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, c0, s, 0, 0, 0);
-      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c1, s, 0, 0, 0);
-      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, c0, s, 0, 0, 0);
-      s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c0, s, 0, 0, 0);
+      f4v sacc = {0.f, 0.f, 0.f, 0.f};
+      sacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, c1, sacc, 0, 0, 0);
+      sacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c2, sacc, 0, 0, 0);
+      sacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, c0, sacc, 0, 0, 0);
+      sacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c1, sacc, 0, 0, 0);
+      sacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, c0, sacc, 0, 0, 0);
+      sacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, c0, sacc, 0, 0, 0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[t][q] += (double)s[q];
+      for (int q = 0; q < 4; ++q) acc[t][q] += (double)sacc[q];
     }
   }
   double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
     if (!bv[t]) continue;
-    const int j = bq[t] * 16 + (lane & 15);
+    const bool second = bo[t] & 1;
+    double* o = second ? out + A.part_pair : out;
+    const int j = ((bo[t] >> 1) & 0x7FFF) * 16 + (lane & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = bp[t] * 16 + 4 * (lane >> 4) + q;
-      if (i < ni && j < nj) out[(size_t)i * A.part_ld + j] = acc[t][q];
+      const int i = (bo[t] >> 16) * 16 + 4 * (lane >> 4) + q;
+      if (i < ni && j < (second ? ni : nj)) o[(size_t)i * A.part_ld + j] = acc[t][q];
     }
   }
 }
@@ -1437,17 +1540,35 @@ __global__ void __launch_bounds__(RES_THREADS) k_residual(ResArgs A) {
   }
 }
 
-// per element: active = max_{i<J} res_i > tol ; count of active elements
+// per element: active = max_{i<J} res_i > tol ; count of active elements; the
+// Rayleigh-Ritz breakdowns (status 2) since the last check are added to count[2]
+// and their flags cleared
 __global__ void k_check(const ElemDev* elems, int n_elem, int* active, double tol, int* count,
-                        double* maxres, int* iter_count) {
+                        double* maxres, int* iter_count, int* status) {
   __shared__ double sh[16];
+  if (threadIdx.x == 0) {
+    int brk = 0;
+    for (int e = 0; e < n_elem; ++e)
+      if (status[e] != 0) {
+        ++brk;
+        status[e] = 0;
+      }
+    count[2] += brk;
+  }
+  __syncthreads();
   for (int e = 0; e < n_elem; ++e) {
     const ElemDev& E = elems[e];
     const int KP = E.kmax3 + 2;
     const double* res = E.small + SmallLayout::vec(KP) + VS_RES * KP;
     double m = 0.0;
-    for (int i = threadIdx.x; i < E.J; i += blockDim.x) m = fmax(m, res[i]);
+    int bad = 0;
+    for (int i = threadIdx.x; i < E.J; i += blockDim.x) {
+      const double r = res[i];
+      bad |= !(r == r);          // fmax drops NaN: flag it separately
+      m = fmax(m, r);
+    }
     m = block_max(m, sh);
+    if (__syncthreads_or(bad)) m = __builtin_nan("");
     if (threadIdx.x == 0) {
       if (active[e] && !(m <= tol)) {
       } else {
@@ -1485,6 +1606,7 @@ struct CopyArgs {
   int ncol;                   // column code
   int to_packed;              // 1: block -> ptr
   int mode;
+  long long ld;               // mode 0: > 0 caller leading dimension (element blocks ld * ncol apart)
 };
 
 template <typename T>
@@ -1509,8 +1631,14 @@ __global__ void __launch_bounds__(256) k_copy(CopyArgs A) {
     d[r] = b[gr];
     return;
   }
-  const long long base = (A.elem_only >= 0 || !A.off) ? 0 : A.off[e] * A.off_mult;
-  T* p = reinterpret_cast<T*>(A.ptr) + base + (size_t)j * nrows + r;
+  long long base, cstride = nrows;
+  if (A.ld > 0) {
+    base = A.elem_only >= 0 ? 0 : (long long)e * A.ld * ncol;
+    cstride = A.ld;
+  } else {
+    base = (A.elem_only >= 0 || !A.off) ? 0 : A.off[e] * A.off_mult;
+  }
+  T* p = reinterpret_cast<T*>(A.ptr) + base + (size_t)j * cstride + r;
   if (A.to_packed) *p = b[gr];
   else b[gr] = *p;
 }
@@ -1546,14 +1674,45 @@ __global__ void __launch_bounds__(256) k_convert(const ElemDev* elems, int src_b
   else reinterpret_cast<float*>(E.blk[dst_blk])[o] = float(v);
 }
 
-// J values per element from the small-vector slots into packed outputs
+// Seeded Gaussian start: value (row r, column j) of element g = e + elem_base is a
+// Box-Muller normal from two SplitMix64 outputs of the counter (seed, g, j, r), so
+// the block does not depend on how the batch is split into element groups.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_random_block(const ElemDev* elems, int blk, unsigned long long seed,
+                                                       int elem_base) {
+  const int e = blockIdx.z;
+  const ElemDev& E = elems[e];
+  const int j = blockIdx.y;
+  if (j >= E.K) return;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= E.N) return;
+  const unsigned long long key =
+      splitmix64(seed ^ splitmix64(((unsigned long long)(e + elem_base) << 32) | (unsigned)j)) ^ (unsigned long long)r;
+  const unsigned long long h1 = splitmix64(2 * key), h2 = splitmix64(2 * key + 1);
+  // u1 in (0, 1], u2 in [0, 1)
+  const double u1 = ((double)(h1 >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+  const double u2 = (double)(h2 >> 11) * (1.0 / 9007199254740992.0);
+  const double v = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+  reinterpret_cast<T*>(E.blk[blk])[(size_t)j * E.ld + r] = T(v);
+}
+
+// J (all = 0) or J + g (all = 1) values per element from the small-vector slots
+// into packed outputs
 __global__ void k_extract(const ElemDev* elems, const long long* off, int slot0, double* out0,
-                          int slot1, double* out1) {
+                          int slot1, double* out1, int all) {
   const int e = blockIdx.x;
   const ElemDev& E = elems[e];
   const int KP = E.kmax3 + 2;
   const double* vec = E.small + SmallLayout::vec(KP);
-  for (int i = threadIdx.x; i < E.J; i += blockDim.x) {
+  const int n = all ? E.K : E.J;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     if (out0) out0[off[e] + i] = vec[slot0 * KP + i];
     if (out1) out1[off[e] + i] = vec[slot1 * KP + i];
   }
@@ -1614,41 +1773,31 @@ static bool set_lds_limit(const void* fn, int bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
 }
 
-// FP32 Grams stage 18, 26 or 36 values per thread (up to 288, 416, 576 columns); the
-// wider stagings exist only for up to 6 and 4 output blocks per wave, where they fit
-// the registers without spilling
+// Gram instantiations: FP64 blocks per wave {1,2,3,4,6,8,12} x staged values
+// per thread {4,8,12} (up to 128, 256, 384 columns); BF16x3 {1,2,3,4,6,8} x {8,18}
+// (up to 128, 288 columns), which keeps the FP32 staging and the FP64 accumulators
+// in registers.
 template <int MB>
 static void gram_attrs() {
-  set_lds_limit((const void*)k_gram<double, MB, 9>, 96000);
-  set_lds_limit((const void*)k_gram<double, MB, 18>, 96000);
-  if constexpr (MB == 8) {
-    set_lds_limit((const void*)k_gram<double, 12, 9>, 96000);
-    set_lds_limit((const void*)k_gram<double, 12, 18>, 96000);
+  set_lds_limit((const void*)k_gram<double, MB, 4>, 64000);
+  set_lds_limit((const void*)k_gram<double, MB, 8>, 64000);
+  set_lds_limit((const void*)k_gram<double, MB, 12>, 64000);
+  if constexpr (MB <= 8) {
+    set_lds_limit((const void*)k_gram_bf16<MB, 8>, 96000);
+    set_lds_limit((const void*)k_gram_bf16<MB, 18>, 96000);
   }
-  set_lds_limit((const void*)k_gram_bf16<MB, 18>, 144000);
-  if constexpr (MB <= 6) set_lds_limit((const void*)k_gram_bf16<MB, 26>, 144000);
-  if constexpr (MB <= 4) set_lds_limit((const void*)k_gram_bf16<MB, 36>, 144000);
 }
 
 template <int MB>
-static int launch_gram_bf16(dim3 g, size_t lds, hipStream_t s, const GramArgs& ga, int nc) {
-  if (nc <= 288) {
-    hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g, dim3(GP_THREADS), lds, s, ga);
-    return DG_OK;
+static void launch_gram_mb(int prec, int pf, dim3 g, size_t lds, hipStream_t s, const GramArgs& ga) {
+  if (prec == DG_FP64) {
+    if (pf <= 4) hipLaunchKernelGGL((k_gram<double, MB, 4>), g, dim3(GP_THREADS), lds, s, ga);
+    else if (pf <= 8) hipLaunchKernelGGL((k_gram<double, MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
+    else hipLaunchKernelGGL((k_gram<double, MB, 12>), g, dim3(GP_THREADS), lds, s, ga);
+  } else if constexpr (MB <= 8) {
+    if (pf <= 8) hipLaunchKernelGGL((k_gram_bf16<MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
+    else hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g, dim3(GP_THREADS), lds, s, ga);
   }
-  if constexpr (MB <= 6) {
-    if (nc <= 416) {
-      hipLaunchKernelGGL((k_gram_bf16<MB, 26>), g, dim3(GP_THREADS), lds, s, ga);
-      return DG_OK;
-    }
-  }
-  if constexpr (MB <= 4) {
-    hipLaunchKernelGGL((k_gram_bf16<MB, 36>), g, dim3(GP_THREADS), lds, s, ga);
-    return DG_OK;
-  }
-  set_error("Gram: no FP32 staging variant for " + std::to_string(nc) + " columns at " + std::to_string(MB) +
-            " blocks per wave");
-  return DG_ERR_SHAPE;
 }
 
 // dynamic-LDS limits of every kernel variant, set once before any launch (and so
@@ -1661,6 +1810,7 @@ void init_kernel_attributes() {
     gram_attrs<4>();
     gram_attrs<6>();
     gram_attrs<8>();
+    gram_attrs<12>();
     set_lds_limit((const void*)k_rr_lds<true>, kRRLdsBytes);
     return true;
   }();
@@ -1668,6 +1818,43 @@ void init_kernel_attributes() {
 }
 
 // pair: also S^T S (to out_off_ss) from the same staging of [S | T]
+// Tile side for a Gram launch: the tb that stages the fewest columns in total
+// (over the tiles of every element shape in the launch) while each tile's blocks
+// fit 8 waves x max_blocks and its staged columns max_cols.
+struct GramPlan {
+  int tb = 1, maxblk = 0, maxnc = 0, ntiles = 0;
+};
+
+static GramPlan plan_gram_tiles(const std::vector<int>& bis, int bj_max, int sym, int same, int pair,
+                                int max_blocks, int max_cols) {
+  int bi_max = 0;
+  for (int b : bis) bi_max = std::max(bi_max, b);
+  GramPlan best;
+  long long best_staged = -1;
+  for (int tb = std::max(bi_max, bj_max); tb >= 1; --tb) {
+    GramPlan pl;
+    pl.tb = tb;
+    long long staged = 0;
+    for (int bi : bis) {
+      const int bj = sym ? bi : bj_max;
+      const int nt = gram_ntiles(bi, bj, tb, sym);
+      if (bi == bi_max) pl.ntiles = nt;
+      for (int t = 0; t < nt; ++t) {
+        const GramTile g = gram_tile(t, bi, bj, tb, sym, same, pair);
+        pl.maxblk = std::max(pl.maxblk, g.nloc * (pair ? 2 : 1));
+        pl.maxnc = std::max(pl.maxnc, g.ncA + g.ncB + g.ncC);
+        if (bi == bi_max) staged += g.ncA + g.ncB + g.ncC;
+      }
+    }
+    if (pl.maxblk > 8 * max_blocks || pl.maxnc > max_cols) continue;
+    if (best_staged < 0 || staged < best_staged) {
+      best = pl;
+      best_staged = staged;
+    }
+  }
+  return best;
+}
+
 static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                      long long out_off, const int* active, int rows_e, int sym, bool pair = false,
                      long long out_off_ss = 0) {
@@ -1679,38 +1866,41 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   const bool same = S.nb == T.nb && kS == kT &&
                     std::equal(S.blk, S.blk + S.nb, T.blk);
   if (sym && maxni != maxnj) { set_error("symmetric Gram of a non-square shape"); return DG_ERR_ARG; }
-  const int bi = (maxni + 15) / 16, bj = (maxnj + 15) / 16;
-  const int nc = bi * 16 + (same ? 0 : bj * 16);
-  if (nc > GP_MAXCOL) { set_error("Gram: more columns than one workgroup stages"); return DG_ERR_SHAPE; }
-  const int nblk = sym ? bi * (bi + 1) / 2 : bi * bj;
   const long long part_sq = (long long)c.gram_part_ld * c.gram_part_ld;
   if (pair) {
-    // one staging for both products (FP64, symmetric, T != S) when the doubled block
-    // list takes at most two workgroups per row panel (each stages [S | T]; measured
-    // slower than two Grams beyond that) and the partial area holds both; else two
-    // separate Grams
-    const bool fits = prec == DG_FP64 && sym && !same && 2 * nblk <= 2 * 8 * 12 &&
-                      c.gram_part_stride >= 2 * part_sq;
+    // both products from one staging of S (symmetric, T != S) when the partial area
+    // holds both sets of partial sums; else two separate Grams
+    const bool fits = sym && !same && c.gram_part_stride >= 2 * part_sq;
     if (!fits) {
       if (int st = gram_impl(c, prec, S, kS, S, kS, out_off_ss, active, rows_e, sym)) return st;
       return gram_impl(c, prec, S, kS, T, kT, out_off, active, rows_e, sym);
     }
   }
-  const int nblk_all = pair ? 2 * nblk : nblk;
-  // output blocks per wave: the smallest instantiated count that covers the result,
-  // else 8 (larger results take several workgroups, each re-reading the columns)
-  // (FP32 data with 289..416 staged columns: at most 6, which keeps the 26 staged values
-  // per thread and the accumulators in registers; 12 only for the FP64 pair)
+  // block-row counts of the element shapes in this launch
+  std::vector<int> bis;
+  for (int e = 0; e < c.n_elem; ++e) {
+    const int ke = kS > 0 ? kS : (kS == 0 ? c.K[e] : c.J[e]);
+    const int b = (S.nb * ke + 15) / 16;
+    if (std::find(bis.begin(), bis.end(), b) == bis.end()) bis.push_back(b);
+  }
+  const int bj_max = (maxnj + 15) / 16;
+  // FP64: up to 12 blocks per wave (16 spill registers) and 384 staged columns; BF16x3: 8 and 288
+  const int cap_blocks = prec == DG_FP64 ? 12 : 8;
+  const int cap_cols = prec == DG_FP64 ? GP_MAXCOL : 288;
+  const GramPlan pl = plan_gram_tiles(bis, bj_max, sym, same ? 1 : 0, pair ? 1 : 0, cap_blocks, cap_cols);
+  if (pl.maxblk == 0) {
+    set_error("Gram: no tile fits the per-workgroup limits");
+    return DG_ERR_SHAPE;
+  }
   static const int kMaxbList[] = {1, 2, 3, 4, 6, 8, 12};
-  const int maxb_top = pair ? 12 : (prec == DG_FP64 || nc <= 288 ? 8 : (nc <= 416 ? 6 : 4));
-  int maxb = maxb_top;
+  int maxb = cap_blocks;
   for (int m : kMaxbList)
-    if (m <= maxb_top && 8 * m >= nblk_all) {
+    if (m <= cap_blocks && 8 * m >= pl.maxblk) {
       maxb = m;
       break;
     }
-  const int cap = 8 * maxb;
-  const int groups = (nblk_all + cap - 1) / cap;
+  const int pf = prec == DG_FP64 ? (pl.maxnc + 31) / 32 : (pl.maxnc + 15) / 16;
+  const int groups = pl.ntiles;
   // row-range split: about 1024 workgroups over the launch, at least 256 rows each; the
   // autotuner below may replace it by half or twice that for this Gram shape (the pair
   // keeps two sets of partials)
@@ -1722,55 +1912,38 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
       (pair ? 1 : 0);
   auto tuned = c.gram_split_table.find(key);
   if (tuned != c.gram_split_table.end()) nsplit = tuned->second;
-  GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, rows_e, sym, same ? 1 : 0, cap, c.gram_part,
-              c.gram_part_stride, c.gram_part_ld, pair ? 1 : 0, 0};
+  GramArgs ga{c.elems_dev, active, S, T, kS, kT, nsplit, rows_e, sym, same ? 1 : 0, pl.tb, pl.ntiles,
+              c.n_elem, c.gram_part, c.gram_part_stride, c.gram_part_ld, pair ? 1 : 0, 0};
+  // algorithmic flops: 2 r n_i n_j per product, n (n + 1) r for a symmetric n x n result
   double flops = 0.0;
   for (int e = 0; e < c.n_elem; ++e) {
     if (active && !c.active_host.empty() && !c.active_host[e]) continue;
     const int ke = kS > 0 ? kS : (kS == 0 ? c.K[e] : c.J[e]);
     const int kt = kT > 0 ? kT : (kT == 0 ? c.K[e] : c.J[e]);
     const double r = rows_e ? (double)c.en[0][e] * c.en[1][e] * c.en[2][e] : (double)c.N[e];
-    flops += 2.0 * r * (S.nb * ke) * (T.nb * kt) * (pair ? 2.0 : 1.0);
+    const double ni = S.nb * ke, nj = T.nb * kt;
+    flops += (sym ? r * ni * (ni + 1.0) : 2.0 * r * ni * nj) * (pair ? 2.0 : 1.0);
   }
-  const size_t lds = (size_t)GP_R * (nc + 1) * sizeof(double) + (size_t)nc * sizeof(void*);
-  const size_t lds_bf16 = (size_t)3 * nc * GB_PITCH * 2 + (size_t)nc * sizeof(void*);
+  const size_t lds = prec == DG_FP64 ? (size_t)GP_R * (pl.maxnc + 1) * sizeof(double) + (size_t)pl.maxnc * sizeof(void*)
+                                     : (size_t)3 * pl.maxnc * GB_PITCH * 2 + (size_t)pl.maxnc * sizeof(void*);
   auto launch = [&](int ns) -> int {
     ga.nsplit = ns;
     ga.part_pair = ns * part_sq;
-    dim3 g1(groups, ns, c.n_elem);
-#define DG_GRAM_CASE(MB)                                                                 \
-  case MB:                                                                               \
-    if (prec == DG_FP64) {                                                               \
-      if (nc <= 288)                                                                     \
-        hipLaunchKernelGGL((k_gram<double, MB, 9>), g1, dim3(GP_THREADS), lds, c.stream, ga); \
-      else                                                                               \
-        hipLaunchKernelGGL((k_gram<double, MB, 18>), g1, dim3(GP_THREADS), lds, c.stream, ga); \
-    } else if (int st = launch_gram_bf16<MB>(g1, lds_bf16, c.stream, ga, nc)) {          \
-      return st;                                                                         \
-    }                                                                                    \
-    break;
+    // 1D grid: tiles x row ranges (split, element), the row ranges padded to a multiple of 8
+    const long long n_rr8 = ((long long)ns * c.n_elem + 7) / 8 * 8;
+    dim3 g1((unsigned)(groups * n_rr8));
     switch (maxb) {
-      case 12:
-        if (prec != DG_FP64) {
-          set_error("Gram: unsupported block count");
-          return DG_ERR_SHAPE;
-        }
-        if (nc <= 288)
-          hipLaunchKernelGGL((k_gram<double, 12, 9>), g1, dim3(GP_THREADS), lds, c.stream, ga);
-        else
-          hipLaunchKernelGGL((k_gram<double, 12, 18>), g1, dim3(GP_THREADS), lds, c.stream, ga);
-        break;
-      DG_GRAM_CASE(1)
-      DG_GRAM_CASE(2)
-      DG_GRAM_CASE(3)
-      DG_GRAM_CASE(4)
-      DG_GRAM_CASE(6)
-      DG_GRAM_CASE(8)
+      case 1: launch_gram_mb<1>(prec, pf, g1, lds, c.stream, ga); break;
+      case 2: launch_gram_mb<2>(prec, pf, g1, lds, c.stream, ga); break;
+      case 3: launch_gram_mb<3>(prec, pf, g1, lds, c.stream, ga); break;
+      case 4: launch_gram_mb<4>(prec, pf, g1, lds, c.stream, ga); break;
+      case 6: launch_gram_mb<6>(prec, pf, g1, lds, c.stream, ga); break;
+      case 8: launch_gram_mb<8>(prec, pf, g1, lds, c.stream, ga); break;
+      case 12: launch_gram_mb<12>(prec, pf, g1, lds, c.stream, ga); break;
       default:
         set_error("Gram: unsupported block count");
         return DG_ERR_SHAPE;
     }
-#undef DG_GRAM_CASE
     return DG_OK;
   };
   if (tuned == c.gram_split_table.end() && c.autotune && !c.capturing) {
@@ -1811,8 +1984,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     c.gram_split_table[key] = best_ns;
     nsplit = best_ns;
     if (c.log_level > 0)
-      fprintf(stderr, "[dg] gram autotune %dx%d sym=%d prec=%d pair=%d: split %d (%.3f ms)\n", maxni, maxnj, sym,
-              prec, pair ? 1 : 0, best_ns, best);
+      fprintf(stderr, "[dg] gram autotune %dx%d sym=%d prec=%d pair=%d tile=%d (%d tiles, %d blocks/wg): split %d "
+              "(%.3f ms)\n", maxni, maxnj, sym, prec, pair ? 1 : 0, pl.tb, groups, pl.maxblk, best_ns, best);
   }
   TimedScope ts(c, TC_GRAM, flops);
   if (int st = launch(nsplit)) return st;
@@ -1933,15 +2106,16 @@ int launch_residual(Ctx& c, int prec, int x_blk, int hx_blk, int ncol, const int
 
 int launch_check(Ctx& c, int* active, double tol) {
   hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, c.stream, c.elems_dev, c.n_elem, active, tol,
-                     c.dev_count, c.dev_maxres, c.dev_iters);
+                     c.dev_count, c.dev_maxres, c.dev_iters, c.dev_status);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
-int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed) {
+int launch_copy_ext(Ctx& c, int prec, int blk, const void* ptr, int elem, int ncol, int to_packed,
+                    long long ld) {
   int maxk, maxN, maxE;
   max_dims(c, ncol, &maxk, &maxN, &maxE);
-  CopyArgs a{c.elems_dev, blk, 0, const_cast<void*>(ptr), c.dev_off_grid, ncol, elem, ncol, to_packed, 0};
+  CopyArgs a{c.elems_dev, blk, 0, const_cast<void*>(ptr), c.dev_off_grid, ncol, elem, ncol, to_packed, 0, ld};
   dim3 g((maxN + 255) / 256, maxk, elem >= 0 ? 1 : c.n_elem);
   if (prec == DG_FP64) hipLaunchKernelGGL(k_copy<double>, g, dim3(256), 0, c.stream, a);
   else hipLaunchKernelGGL(k_copy<float>, g, dim3(256), 0, c.stream, a);
@@ -1958,7 +2132,7 @@ int launch_copy_packed(Ctx& c, int prec, int blk, const double* ptr, const long 
     if (prec == DG_FP64) hipLaunchKernelGGL(k_copy_in64<double>, g, dim3(256), 0, c.stream, c.elems_dev, blk, ptr, off, ncol);
     else hipLaunchKernelGGL(k_copy_in64<float>, g, dim3(256), 0, c.stream, c.elems_dev, blk, ptr, off, ncol);
   } else {
-    CopyArgs a{c.elems_dev, blk, 0, const_cast<double*>(ptr), off, 1, -1, ncol, 1, 0};
+    CopyArgs a{c.elems_dev, blk, 0, const_cast<double*>(ptr), off, 1, -1, ncol, 1, 0, 0};
     hipLaunchKernelGGL(k_copy<double>, g, dim3(256), 0, c.stream, a);
   }
   DG_HIP(hipGetLastError());
@@ -1968,7 +2142,7 @@ int launch_copy_packed(Ctx& c, int prec, int blk, const double* ptr, const long 
 int launch_gather_e(Ctx& c, int src_blk, int dst_blk) {
   int maxk, maxN, maxE;
   max_dims(c, -1, &maxk, &maxN, &maxE);
-  CopyArgs a{c.elems_dev, src_blk, dst_blk, nullptr, nullptr, 0, -1, -1, 0, 2};
+  CopyArgs a{c.elems_dev, src_blk, dst_blk, nullptr, nullptr, 0, -1, -1, 0, 2, 0};
   dim3 g((maxE + 255) / 256, maxk, c.n_elem);
   hipLaunchKernelGGL(k_copy<double>, g, dim3(256), 0, c.stream, a);
   DG_HIP(hipGetLastError());
@@ -1985,6 +2159,18 @@ int launch_copy_rows_out(Ctx& c, int blk, double* out) {
   return DG_OK;
 }
 
+int launch_random_block(Ctx& c, int prec, int blk, unsigned long long seed) {
+  int maxk, maxN, maxE;
+  max_dims(c, 0, &maxk, &maxN, &maxE);
+  dim3 g((maxN + 255) / 256, maxk, c.n_elem);
+  if (prec == DG_FP64)
+    hipLaunchKernelGGL(k_random_block<double>, g, dim3(256), 0, c.stream, c.elems_dev, blk, seed, c.elem_base);
+  else
+    hipLaunchKernelGGL(k_random_block<float>, g, dim3(256), 0, c.stream, c.elems_dev, blk, seed, c.elem_base);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
 int launch_convert(Ctx& c, int src_blk, int src_prec, int dst_blk, int dst_prec, int ncol) {
   int maxk, maxN, maxE;
   max_dims(c, ncol, &maxk, &maxN, &maxE);
@@ -1997,14 +2183,21 @@ int launch_convert(Ctx& c, int src_blk, int src_prec, int dst_blk, int dst_prec,
 
 int launch_extract_eig(Ctx& c, double* eig, double* resid) {
   hipLaunchKernelGGL(k_extract, dim3(c.n_elem), dim3(128), 0, c.stream, c.elems_dev, c.dev_off_eig,
-                     (int)VS_THETA, eig, (int)VS_RES, resid);
+                     (int)VS_THETA, eig, (int)VS_RES, resid, 0);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_extract_kall(Ctx& c, double* theta, double* resid) {
+  hipLaunchKernelGGL(k_extract, dim3(c.n_elem), dim3(128), 0, c.stream, c.elems_dev, c.dev_off_kall,
+                     (int)VS_THETA, theta, (int)VS_RES, resid, 1);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
 int launch_extract_theta(Ctx& c, double* out) {
   hipLaunchKernelGGL(k_extract, dim3(c.n_elem), dim3(128), 0, c.stream, c.elems_dev, c.dev_off_eig,
-                     (int)VS_THETA, out, (int)VS_THETA, (double*)nullptr);
+                     (int)VS_THETA, out, (int)VS_THETA, (double*)nullptr, 0);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

@@ -505,6 +505,16 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
   hipStream_t s = c.stream;
   const int* act_host = (active && !c.active_host.empty()) ? c.active_host.data() : nullptr;
   const int* iota = c.iota_dev;
+  if (c.timing && !c.capturing) {
+    // algorithmic bytes of the state applications: read psi, write H psi, V and the
+    // projectors (nnz values + int32 indices) amortised over the J wanted states
+    const double sz = sizeof(T);
+    for (int e = 0; e < c.n_elem; ++e) {
+      if ((elem >= 0 && e != elem) || (act_host && !act_host[e])) continue;
+      const double N = c.N[e], k = ncols > 0 ? ncols : c.K[e], J = c.J[e];
+      c.tacc.hpsi_alg += k * (2.0 * N * sz + N * sz / J + c.nnz[e] * (sz + 4.0) / J);
+    }
+  }
   // projector overlaps first (reads x only)
   {
     NlArgs na{c.elems_dev, active, in_blk, out_blk, ncols, elem};

@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -138,7 +139,7 @@ struct Plan {
       off_de,
       off_minpiv;
   int n_extra;
-  size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_lists;
+  size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_offkall, off_lists;
   size_t off_ckpt, off_part;
   size_t ckpt_block_bytes;
   int n_ckpt;
@@ -176,10 +177,23 @@ static int validate(int n_elem, const dg_element_desc* d) {
       set_error("element " + std::to_string(e) + ": n_states out of range");
       return DG_ERR_ARG;
     }
+    // J_k ALBs on E_k need at least J_k grid points there: the restriction of J_k
+    // eigenvectors to fewer points is rank deficient by construction
+    const long long ne = (long long)x.elem_n[0] * x.elem_n[1] * x.elem_n[2];
+    if (x.n_states > ne) {
+      set_error("element " + std::to_string(e) + ": n_states " + std::to_string(x.n_states) +
+                " exceeds the " + std::to_string(ne) + " grid points of E_k (the ALBs would be rank deficient)");
+      return DG_ERR_SHAPE;
+    }
     if (!x.v_eff) {
       set_error("element " + std::to_string(e) + ": v_eff is NULL");
       return DG_ERR_ARG;
     }
+    for (int i = 0; i < N; ++i)
+      if (!std::isfinite(x.v_eff[i])) {
+        set_error("element " + std::to_string(e) + ": v_eff[" + std::to_string(i) + "] is not finite");
+        return DG_ERR_NUMERIC;
+      }
     if (x.n_proj < 0 || (x.n_proj > 0 && (!x.proj_ptr || !x.proj_idx || !x.proj_val || !x.gamma))) {
       set_error("element " + std::to_string(e) + ": projector arrays missing");
       return DG_ERR_ARG;
@@ -194,7 +208,15 @@ static int validate(int n_elem, const dg_element_desc* d) {
           set_error("element " + std::to_string(e) + ": proj_ptr not monotone");
           return DG_ERR_ARG;
         }
+        if (!std::isfinite(x.gamma[p])) {
+          set_error("element " + std::to_string(e) + ": gamma is not finite");
+          return DG_ERR_NUMERIC;
+        }
         for (int64_t t = x.proj_ptr[p]; t < x.proj_ptr[p + 1]; ++t) {
+          if (!std::isfinite(x.proj_val[t])) {
+            set_error("element " + std::to_string(e) + ": projector value is not finite");
+            return DG_ERR_NUMERIC;
+          }
           if (x.proj_idx[t] < 0 || x.proj_idx[t] >= N ||
               (t > x.proj_ptr[p] && x.proj_idx[t] <= x.proj_idx[t - 1])) {
             set_error("element " + std::to_string(e) + ": projector indices must be ascending and in range");
@@ -265,6 +287,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_offalb = take(sizeof(long long) * (n_elem + 1));
   P.off_offgrid = take(sizeof(long long) * (n_elem + 1));
   P.off_offeig = take(sizeof(long long) * (n_elem + 1));
+  P.off_offkall = take(sizeof(long long) * (n_elem + 1));
   P.off_lists = take(sizeof(int) * n_elem);
   size_t ckpt_block = 0;
   for (int e = 0; e < n_elem; ++e) {
@@ -336,7 +359,9 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
     return DG_ERR_OOM;
   }
   init_kernel_attributes();
-  Ctx* c = new Ctx();
+  // owned here until every staging step has succeeded (no leak on an early return)
+  std::unique_ptr<Ctx> owner(new Ctx());
+  Ctx* c = owner.get();
   c->stream = (hipStream_t)stream;
   c->n_elem = n_elem;
   c->arena = (char*)arena;
@@ -420,7 +445,8 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
             }
         for (double r : rowsum) nl = std::max(nl, r);
       }
-      E.bup = kin + std::max(vmax, 0.0) + nl + 1e-6;
+      E.bup_base = kin + nl + 1e-6;
+      E.bup = E.bup_base + std::max(vmax, 0.0);
     }
     E.v64 = (const double*)(A + p.off_v64);
     E.v32 = (const float*)(A + p.off_v32);
@@ -499,6 +525,9 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   keep64.emplace_back(c->off_eig.begin(), c->off_eig.end());
   if ((st = cpy(P.off_offeig, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
   c->dev_off_eig = (long long*)(A + P.off_offeig);
+  keep64.emplace_back(c->off_kall.begin(), c->off_kall.end());
+  if ((st = cpy(P.off_offkall, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
+  c->dev_off_kall = (long long*)(A + P.off_offkall);
   // shape classes
   std::map<std::tuple<int, int, int>, std::vector<int>> cls;
   for (int e = 0; e < n_elem; ++e) cls[{d[e].n[0], d[e].n[1], d[e].n[2]}].push_back(e);
@@ -561,10 +590,9 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   hipError_t se = hipStreamSynchronize(s);
   if (se != hipSuccess) {
     set_error(std::string("hipStreamSynchronize: ") + hipGetErrorString(se));
-    delete c;
     return DG_ERR_HIP;
   }
-  *out = c;
+  *out = owner.release();
   return DG_OK;
 }
 

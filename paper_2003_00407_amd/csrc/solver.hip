@@ -28,10 +28,21 @@ static int sync_read(Ctx& c, void* dst, const void* src, size_t bytes) {
 // resolves with its element's layout: 0 G, 1 A, 2 U, 3 V, 4 C.
 static long long small_code(int which) { return -1 - which; }
 
-int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y) {
+int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, long long ldx, void* y, long long ldy) {
   if (!x || !y) {
     set_error("x or y is NULL");
     return DG_ERR_ARG;
+  }
+  if (ldx < 0 || ldy < 0) {
+    set_error("ldx and ldy must be >= 0");
+    return DG_ERR_ARG;
+  }
+  for (int e = 0; e < c.n_elem; ++e) {
+    if (elem >= 0 && e != elem) continue;
+    if ((ldx > 0 && ldx < c.N[e]) || (ldy > 0 && ldy < c.N[e])) {
+      set_error("ldx / ldy below the grid size N_k of element " + std::to_string(e + c.elem_base));
+      return DG_ERR_ARG;
+    }
   }
   if (elem < -1 || elem >= c.n_elem) {
     set_error("elem out of range");
@@ -49,10 +60,11 @@ int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, void* y) {
     }
   }
   int st;
-  // copy in (packed -> block W), apply W -> HW, copy out
-  if ((st = launch_copy_ext(c, prec, B_W, x, elem, n_vec, 0))) return st;
+  // copy in (caller layout -> block W), apply W -> HW, copy out; X and the solver's
+  // outputs are not touched
+  if ((st = launch_copy_ext(c, prec, B_W, x, elem, n_vec, 0, ldx))) return st;
   if ((st = launch_hpsi(c, elem, n_vec, prec, B_W, B_HW, nullptr))) return st;
-  if ((st = launch_copy_ext(c, prec, B_HW, y, elem, n_vec, 1))) return st;
+  if ((st = launch_copy_ext(c, prec, B_HW, y, elem, n_vec, 1, ldy))) return st;
   return DG_OK;
 }
 
@@ -99,8 +111,19 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   return launch_permute(c, perm, active);
 }
 
+// reads [active, NaN, Rayleigh-Ritz breakdowns, -] of the last check
+static int read_counts(Ctx& c, int* cnt) { return sync_read(c, cnt, c.dev_count, 4 * sizeof(int)); }
+
+// zero the breakdown counter before a stage (outside any captured graph)
+static int reset_breakdowns(Ctx& c) {
+  DG_HIP(hipMemsetAsync(c.dev_count + 2, 0, sizeof(int), c.stream));
+  return DG_OK;
+}
+
+// first_stage: the start block is the caller's (or the seeded one); a breakdown of
+// its Rayleigh-Ritz step (X_0^T X_0 not positive definite) is an error
 static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, int* n_done, bool carry_p = false,
-                      int graph_iters = 0) {
+                      int graph_iters = 0, bool first_stage = true) {
   int st;
   int* active = c.dev_active;
   // an FP32 stage stops an element once its residual stops improving (FP32 floor)
@@ -125,6 +148,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
   // matrix is then accurate to about eps * ||H|| / drop_tol in the worst kept direction.
   c.rr_pivot_tol = (prec == DG_FP64) ? 1e-13 : 1e-6;
   c.rr_drop_tol = c.rr_drop_env >= 0.0 ? c.rr_drop_env : (prec == DG_FP64 ? 1e-8 : 1e-4);
+  if ((st = reset_breakdowns(c))) return st;
   if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
   // (the start rotation leaves the block in T1 as P: a carried search direction)
   if ((st = rr_and_rotate(c, prec, 1, active, false))) return st;
@@ -190,10 +214,15 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
       if ((st = launch_check(c, active, tol))) return st;
     }
     checked = false;
-    int cnt[2];
-    if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
+    int cnt[4];
+    if ((st = read_counts(c, cnt))) return st;
     if (cnt[1] > 0) {
       set_error("non-finite residual in " + std::to_string(cnt[1]) + " element(s)");
+      return DG_ERR_NUMERIC;
+    }
+    if (it == 1 && first_stage && cnt[2] > 0) {
+      set_error("the start block is rank deficient in " + std::to_string(cnt[2]) +
+                " element(s): the Cholesky factorisation of X0^T X0 broke down");
       return DG_ERR_NUMERIC;
     }
     {
@@ -303,10 +332,17 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
   if (iters && (st = sync_read(c, iters, c.dev_iters, sizeof(int) * c.n_elem))) return st;
   if ((st = launch_residual(c, prec, B_X, B_HX, 0, active))) return st;
   if ((st = launch_check(c, active, tol))) return st;
-  int cnt[2];
-  if ((st = sync_read(c, cnt, c.dev_count, sizeof(cnt)))) return st;
+  int cnt[4];
+  if ((st = read_counts(c, cnt))) return st;
   *n_done = c.n_elem - cnt[0];
-  return cnt[1] > 0 ? DG_ERR_NUMERIC : DG_OK;
+  if (cnt[1] > 0) {
+    set_error("non-finite residual in " + std::to_string(cnt[1]) + " element(s)");
+    return DG_ERR_NUMERIC;
+  }
+  // a breakdown mid-run keeps X for that iteration (C = [I; 0; 0]); it is an error
+  // only when the element then fails to converge (checked by the caller's last stage)
+  c.last_breakdowns = cnt[2];
+  return DG_OK;
 }
 
 int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters, int* n_done);
@@ -314,10 +350,6 @@ int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters
 int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters) {
   if (!p || !eig || !resid) {
     set_error("params, eig_dev and resid_dev must be non-NULL");
-    return DG_ERR_ARG;
-  }
-  if (!p->x0_dev) {
-    set_error("x0_dev is required (seeded initial blocks)");
     return DG_ERR_ARG;
   }
   if (p->method != DG_LOBPCG && p->method != DG_CHFSI) {
@@ -332,18 +364,41 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
     set_error("tol must be > 0 and max_iter > 0");
     return DG_ERR_ARG;
   }
+  if (p->warm_start && !c.have_x) {
+    set_error("warm_start needs the vectors of an earlier solve on this context (none, or overwritten by a "
+              "band-energy call)");
+    return DG_ERR_STATE;
+  }
   int st;
   std::vector<int> it1(c.n_elem, 0), it2(c.n_elem, 0);
   int done = 0;
+  // the band energy's checkpoints are overwritten from here on
+  c.be_valid = false;
+  c.solved = false;
+  const bool warm = p->warm_start != 0;
+  // start block into X in the precision of the first stage: the caller's x0, the
+  // seeded device draw, or (warm) the FP64 X of the last solve
+  const int prec0 = p->precision == DG_FP64 ? DG_FP64 : DG_FP32;
+  c.have_x = false;
+  if (warm) {
+    if (prec0 == DG_FP32) {
+      if ((st = launch_convert(c, B_X, DG_FP64, B_W, DG_FP32, KC_K))) return st;
+      int perm[kMaxBlocks] = {B_W, B_X, B_P, B_HX, B_HW, B_HP, B_T0, B_T1};
+      if ((st = launch_permute(c, perm, nullptr))) return st;
+    }
+  } else if (p->x0_dev) {
+    if ((st = launch_copy_packed(c, prec0, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
+  } else {
+    if ((st = launch_random_block(c, prec0, B_X, (unsigned long long)p->seed))) return st;
+  }
+  c.last_breakdowns = 0;
   if (p->precision == DG_FP64) {
-    if ((st = launch_copy_packed(c, DG_FP64, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
     st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it1.data(), &done, false,
                                              std::max(0, p->graph_iters))
                                 : run_chfsi(c, DG_FP64, p->tol, p->max_iter, p->cheb_degree, it1.data(), &done);
     if (st < 0) return st;
   } else {
     const double tmp = p->tol_mixed > 0.0 ? p->tol_mixed : 3e-5;
-    if ((st = launch_copy_packed(c, DG_FP32, B_X, p->x0_dev, c.dev_off_x0, KC_K, 0))) return st;
     st = p->method == DG_LOBPCG ? run_lobpcg(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, it1.data(), &done)
                                 : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree,
                                             it1.data(), &done);
@@ -357,16 +412,35 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
       int perm[kMaxBlocks] = {B_W, B_X, B_P, B_HX, B_HW, B_HP, B_T0, B_T1};
       if ((st = launch_permute(c, perm, nullptr))) return st;
     }
-    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry, std::max(0, p->graph_iters));
+    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry, std::max(0, p->graph_iters),
+                    false);
     if (st < 0) return st;
   }
+  if (done < c.n_elem && c.last_breakdowns > 0) {
+    set_error(std::to_string(c.n_elem - done) + " element(s) did not converge after " +
+              std::to_string(c.last_breakdowns) + " Rayleigh-Ritz breakdown(s) of the X block");
+    return DG_ERR_NUMERIC;
+  }
   c.solved = true;
+  c.have_x = true;
   // outputs: theta, residuals of the J wanted states
   if ((st = launch_extract_eig(c, eig, resid))) return st;
   if (iters)
     for (int e = 0; e < c.n_elem; ++e) iters[e] = it1[e] + it2[e];
   DG_HIP(hipStreamSynchronize(c.stream));
   return done == c.n_elem ? DG_OK : DG_WARN_NOT_CONVERGED;
+}
+
+int get_ritz(Ctx& c, double* theta, double* resid) {
+  if (!c.solved) {
+    set_error("no solve has completed on this context");
+    return DG_ERR_STATE;
+  }
+  if (!theta || !resid) {
+    set_error("theta_dev and resid_dev must be non-NULL");
+    return DG_ERR_ARG;
+  }
+  return launch_extract_kall(c, theta, resid);
 }
 
 int get_vectors(Ctx& c, double* x) {
@@ -396,8 +470,25 @@ int make_alb(Ctx& c, double* alb, double* sval) {
   if ((st = launch_gather_e(c, X, t0))) return st;
   ColSet S0{1, {t0, 0, 0}}, S1{1, {t1, 0, 0}};
   if ((st = launch_gram_rows(c, DG_FP64, S0, KC_J, S0, KC_J, small_code(0), 1, 1))) return st;
+  DG_HIP(hipMemsetAsync(c.dev_status, 0, sizeof(int) * c.n_elem, c.stream));
   if ((st = launch_rr(c, 0, KC_J, KC_J, RR_SVD, nullptr))) return st;
   if ((st = launch_extract_theta(c, sval))) return st;
+  // rank of the restriction: sigma_min <= 1e-10 sigma_max leaves no orthonormal
+  // basis of the restricted span at working precision
+  {
+    std::vector<double> sv((size_t)c.off_eig[c.n_elem]);
+    if ((st = sync_read(c, sv.data(), sval, sizeof(double) * sv.size()))) return st;
+    for (int e = 0; e < c.n_elem; ++e) {
+      const double smax = sv[c.off_eig[e]], smin = sv[c.off_eig[e + 1] - 1];
+      if (!(smin > 1e-10 * smax)) {
+        char buf[160];
+        snprintf(buf, sizeof(buf), "element %d: restriction to E_k is rank deficient (sigma_min %.3e, sigma_max %.3e)",
+                 e + c.elem_base, smin, smax);
+        set_error(buf);
+        return DG_ERR_NUMERIC;
+      }
+    }
+  }
   RotArgs ra{};
   ra.S = S0;
   ra.kS = KC_J;
@@ -414,6 +505,16 @@ int make_alb(Ctx& c, double* alb, double* sval) {
   // second pass (Cholesky QR) restores orthonormality to working precision
   if ((st = launch_gram_rows(c, DG_FP64, S1, KC_J, S1, KC_J, small_code(0), 1, 1))) return st;
   if ((st = launch_rr(c, 0, KC_J, KC_J, RR_CHOLQR, nullptr))) return st;
+  {
+    std::vector<int> stv(c.n_elem);
+    if ((st = sync_read(c, stv.data(), c.dev_status, sizeof(int) * c.n_elem))) return st;
+    for (int e = 0; e < c.n_elem; ++e)
+      if (stv[e] != 0) {
+        set_error("element " + std::to_string(e + c.elem_base) +
+                  ": the Cholesky-QR pass of the ALB orthonormalisation broke down");
+        return DG_ERR_NUMERIC;
+      }
+  }
   ra.S = S1;
   ra.out_blk[0] = t0;
   if ((st = launch_rotate(c, DG_FP64, ra))) return st;

@@ -18,6 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libdgalb.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2003_00407_amd/build.py "
                       "(or __graft_entry__.build())")
+# PyTorch's HIP runtime is loaded before the library, so that the library binds to
+# it (same soname) and the caller's tensors, streams and the library share one
+# runtime instance; loaded the other way round, the process would hold two.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
@@ -28,7 +33,7 @@ DG_OFF_X0, DG_OFF_VEC, DG_OFF_EIG, DG_OFF_ALB, DG_OFF_GRID, DG_OFF_KALL = range(
 
 EXPORTED = [
     "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
-    "dg_query_offsets", "dg_apply_H", "dg_solve_elements", "dg_get_vectors", "dg_make_alb",
+    "dg_query_offsets", "dg_apply_H", "dg_solve_elements", "dg_get_ritz", "dg_get_vectors", "dg_make_alb",
     "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing", "dg_timing_work",
 ]
 
@@ -50,7 +55,8 @@ class Options(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
                 ("tol_mixed", C.c_double), ("max_iter", C.c_int32), ("cheb_degree", C.c_int32),
-                ("x0_dev", C.c_void_p), ("graph_iters", C.c_int32)]
+                ("x0_dev", C.c_void_p), ("graph_iters", C.c_int32), ("seed", C.c_int64),
+                ("warm_start", C.c_int32)]
 
 
 _lib.dg_status_string.restype = C.c_char_p
@@ -63,7 +69,9 @@ _lib.dg_create_elements.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(
 _lib.dg_destroy.argtypes = [C.c_void_p]
 _lib.dg_destroy.restype = None
 _lib.dg_query_offsets.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
-_lib.dg_apply_H.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+_lib.dg_apply_H.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                            C.c_int64]
+_lib.dg_get_ritz.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.dg_solve_elements.argtypes = [C.c_void_p, C.POINTER(SolveParams), C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_int32)]
 _lib.dg_get_vectors.argtypes = [C.c_void_p, C.c_void_p]
@@ -166,6 +174,9 @@ class Elements:
                                        C.c_void_p(self._arena_ptr), C.c_size_t(int(nbytes.value)),
                                        C.c_void_p(self.stream.cuda_stream)), "dg_create_elements")
         self.n_elem = self.hd.n
+        # bumped by every call that replaces the context's band-energy state, so a
+        # backward can tell whether its forward is still the last one
+        self.generation = 0
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -183,32 +194,49 @@ class Elements:
         return self.torch.empty(int(n), dtype=dtype, device=self.device)
 
     # ---- entry points
-    def apply_H(self, x, n_vec: int, prec: int = DG_FP64, elem: int = -1):
-        """y = H x for packed x (N_k x n_vec per element, column-major)."""
+    def apply_H(self, x, n_vec: int, prec: int = DG_FP64, elem: int = -1, ldx: int = 0, ldy: int = 0, y=None):
+        """y = H x; x packed N_k x n_vec per element (ldx = 0) or ldx x n_vec blocks (ldx > 0)."""
         torch = self.torch
         dt = torch.float64 if prec == DG_FP64 else torch.float32
         if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous CUDA tensor of the precision's dtype")
-        y = torch.empty_like(x)
-        _check(_lib.dg_apply_H(self.ctx, elem, n_vec, prec, C.c_void_p(x.data_ptr()),
-                               C.c_void_p(y.data_ptr())), "dg_apply_H")
+        if y is None:
+            if ldy != ldx:
+                raise ValueError("pass y when ldy differs from ldx")
+            y = torch.empty_like(x)
+        _check(_lib.dg_apply_H(self.ctx, elem, n_vec, prec, C.c_void_p(x.data_ptr()), int(ldx),
+                               C.c_void_p(y.data_ptr()), int(ldy)), "dg_apply_H")
         return y
 
-    def solve(self, x0, method: int = DG_LOBPCG, precision: int = DG_FP64, tol: float = 1e-8,
-              tol_mixed: float = 3e-5, max_iter: int = 300, cheb_degree: int = 16, graph_iters: int = 0):
-        """Lowest J_k eigenpairs of every element; returns (eig, resid, iters, status)."""
+    def solve(self, x0=None, method: int = DG_LOBPCG, precision: int = DG_FP64, tol: float = 1e-8,
+              tol_mixed: float = 3e-5, max_iter: int = 300, cheb_degree: int = 16, graph_iters: int = 0,
+              seed: int = 0, warm_start: bool = False):
+        """Lowest J_k eigenpairs of every element; returns (eig, resid, iters, status).
+
+        x0: packed N_k x (J_k+g_k) FP64 start blocks, or None for the seeded device draw
+        (``seed``); warm_start=True starts from the vectors of the last solve."""
         torch = self.torch
-        if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
+        if x0 is not None and (x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous()):
             raise ValueError("x0 must be a contiguous CUDA float64 tensor (packed N_k x (J_k+g_k))")
         n_eig = int(self.offsets(DG_OFF_EIG)[-1])
         eig = self._dev(n_eig, torch.float64)
         res = self._dev(n_eig, torch.float64)
         iters = (C.c_int32 * self.n_elem)()
-        p = SolveParams(method, precision, tol, tol_mixed, max_iter, cheb_degree, C.c_void_p(x0.data_ptr()),
-                        graph_iters)
+        p = SolveParams(method, precision, tol, tol_mixed, max_iter, cheb_degree,
+                        C.c_void_p(x0.data_ptr() if x0 is not None else 0), graph_iters, int(seed),
+                        int(bool(warm_start)))
+        self.generation += 1
         st = _check(_lib.dg_solve_elements(self.ctx, C.byref(p), C.c_void_p(eig.data_ptr()),
                                            C.c_void_p(res.data_ptr()), iters), "dg_solve_elements")
         return eig, res, np.array(list(iters), dtype=np.int32), st
+
+    def ritz(self):
+        """All J_k + g_k Ritz values and residuals of the last solve (packed, DG_OFF_KALL)."""
+        n = int(self.offsets(DG_OFF_KALL)[-1])
+        th = self._dev(n, self.torch.float64)
+        rs = self._dev(n, self.torch.float64)
+        _check(_lib.dg_get_ritz(self.ctx, C.c_void_p(th.data_ptr()), C.c_void_p(rs.data_ptr())), "dg_get_ritz")
+        return th, rs
 
     def vectors(self):
         n = int(self.offsets(DG_OFF_VEC)[-1])
@@ -228,6 +256,7 @@ class Elements:
         """Replace V_eff (packed FP64 CUDA tensor, N_k per element)."""
         if v.dtype != self.torch.float64 or not v.is_cuda or not v.is_contiguous():
             raise ValueError("v must be a contiguous CUDA float64 tensor")
+        self.generation += 1
         _check(_lib.dg_set_potential(self.ctx, C.c_void_p(v.data_ptr())), "dg_set_potential")
 
     def band_energy(self, psi0, f, degree: int, bounds, prec: int = DG_FP64):
@@ -239,6 +268,7 @@ class Elements:
             raise ValueError("bounds needs 3 values per element")
         E = self._dev(self.n_elem, torch.float64)
         self._be_f = f          # must outlive the backward
+        self.generation += 1
         _check(_lib.dg_band_energy(self.ctx, prec, degree, _ptr(bnd, C.c_double), n_vec,
                                    C.c_void_p(psi0.data_ptr()), C.c_void_p(f.data_ptr()),
                                    C.c_void_p(E.data_ptr())), "dg_band_energy")
@@ -259,10 +289,12 @@ class Elements:
     TIMING_CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
 
     def timing(self, enable: bool = True, reset: bool = False):
-        """(ms, launches, algorithmic work) per class since the last reset; then reset/enable."""
+        """(ms, launches, algorithmic work) per class since the last reset; then reset/enable.
+
+        work has 9 entries: the 8 classes, then the H*psi bytes by the per-state count."""
         ms = (C.c_double * 8)()
         n = (C.c_int64 * 8)()
-        w = (C.c_double * 8)()
+        w = (C.c_double * 9)()
         _check(_lib.dg_timing_work(self.ctx, w), "dg_timing_work")
         _check(_lib.dg_timing(self.ctx, int(enable), int(reset), ms, n), "dg_timing")
         return list(ms), list(n), list(w)
@@ -297,10 +329,15 @@ def _band_energy_function():
             E = elements.band_energy(psi0.detach().contiguous(), f, degree, bounds, prec)
             ctx.elements = elements
             ctx.has_v = v is not None
+            ctx.generation = elements.generation
             return E
 
         @staticmethod
         def backward(ctx, gE):
+            if ctx.elements.generation != ctx.generation:
+                raise RuntimeError("BandEnergy.backward: the context ran another band energy, solve or "
+                                   "potential update after this forward; its adjoint state is gone "
+                                   "(run backward before the next forward on the same Elements)")
             dpsi, dv = ctx.elements.band_energy_backward(gE.detach().double().cpu().numpy())
             return (dv if ctx.has_v else None), dpsi, None, None, None, None, None
 

@@ -71,10 +71,51 @@ def test_query_workspace_rejects_bad_input():
     assert "ascending" in d.last_error()
 
 
+def test_more_states_than_element_points_rejected():
+    """J_k ALBs need |E_k| >= J_k grid points (else the restriction is rank deficient)."""
+    import dataclasses
+    d = _lib()
+    el = W.free_electron_element(n_states=7)
+    line = dataclasses.replace(el, elem_lo=(3, 5, 0), elem_n=(1, 1, 6))     # 6 points < 7 states
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([line])
+    assert e.value.status == d.DG_ERR_SHAPE
+    assert "exceeds" in d.last_error()
+    ok = dataclasses.replace(el, elem_lo=(3, 5, 0), elem_n=(1, 1, 16))      # 16 points: accepted
+    assert d.query_workspace([ok]) > 0
+
+
+def test_non_finite_inputs_rejected():
+    import dataclasses
+    d = _lib()
+    el = W.make_config("c1").elements[0]
+    v = el.v_eff.copy()
+    v[123] = np.nan
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([dataclasses.replace(el, v_eff=v)])
+    assert e.value.status == d.DG_ERR_NUMERIC
+    sl = W.small_slab()[0]
+    g = sl.gamma.copy()
+    g[2] = np.inf
+    with pytest.raises(d.DGError) as e:
+        d.query_workspace([dataclasses.replace(sl, gamma=g)])
+    assert e.value.status == d.DG_ERR_NUMERIC
+
+
+def test_solve_params_layout_matches_header():
+    """The ctypes mirror of dg_solve_params has the C layout (field offsets, size)."""
+    d = _lib()
+    P = d.SolveParams
+    assert P.x0_dev.offset == 32 and P.graph_iters.offset == 40
+    assert P.seed.offset == 48 and P.warm_start.offset == 56
+    assert ctypes.sizeof(P) == 64
+
+
 def test_null_context_calls_fail_cleanly():
     d = _lib()
     lib = d._lib
-    assert lib.dg_apply_H(None, -1, 1, 0, None, None) == d.DG_ERR_ARG
+    assert lib.dg_apply_H(None, -1, 1, 0, None, 0, None, 0) == d.DG_ERR_ARG
+    assert lib.dg_get_ritz(None, None, None) == d.DG_ERR_ARG
     assert lib.dg_solve_elements(None, None, None, None, None) == d.DG_ERR_ARG
     assert lib.dg_make_alb(None, None, None) == d.DG_ERR_ARG
     assert lib.dg_get_vectors(None, None) == d.DG_ERR_ARG
