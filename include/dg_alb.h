@@ -89,7 +89,7 @@ typedef struct {
   int32_t elem_n[3];   /* grid points of E_k                                       */
   int32_t n_states;    /* J_k wanted eigenpairs                                    */
   const double *v_eff; /* N values of V_eff on Q_k (Ha)                            */
-  int32_t n_proj;      /* number of projectors b_{I,l} with support in Q_k         */
+  int32_t n_proj;      /* number of projectors b_{I,l} with support in Q_k (<= 480) */
   const int64_t *proj_ptr; /* n_proj+1 offsets into proj_idx / proj_val (CSC of B) */
   const int32_t *proj_idx; /* grid indices, strictly ascending within a projector  */
   const double *proj_val;  /* b_{I,l} values                                       */
@@ -180,6 +180,21 @@ int32_t dg_query_offsets(const dg_ctx *ctx, int32_t kind, int64_t *offsets);
  * element applied.  Errors: DG_ERR_ARG (NULL, ranges, ld too small), DG_ERR_HIP. */
 int32_t dg_apply_H(dg_ctx *ctx, int32_t elem, int32_t n_vec, int32_t prec,
                    const void *x_dev, int64_t ldx, void *y_dev, int64_t ldy);
+
+/* dg_apply_H for callers that cannot allocate device memory (code under HIP
+ * stream capture, tight serving loops): the same y = H x, arguments and layouts
+ * as dg_apply_H, but x is read and y written in place, without staging through
+ * the context's workspace, and the only scratch, the projector overlaps
+ * C = B^T x (nproj_k x n_vec FP64 values per applied element), lives in a
+ * library-owned static device array of 16 MiB per GPU, resolved when the
+ * context is created.  No device memory is allocated by the call.  Calls that
+ * overlap in time on one GPU (any context, any stream) share that array and
+ * race; the array keeps the last call's contents.  The solver's vectors are left
+ * untouched.  Errors: DG_ERR_ARG (as dg_apply_H, and when the overlaps of the
+ * call exceed the array: apply fewer vectors or one element per call),
+ * DG_ERR_HIP. */
+int32_t dg_apply_H_noalloc(dg_ctx *ctx, int32_t elem, int32_t n_vec, int32_t prec,
+                           const void *x_dev, int64_t ldx, void *y_dev, int64_t ldy);
 
 /* Lowest J_k eigenpairs of every H^{Q_k} ("Generating ALB functions";
  * Algorithm 1 or 2).  eig_dev, resid_dev: J_k FP64 values per element

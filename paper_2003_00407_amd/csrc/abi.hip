@@ -80,6 +80,7 @@ struct dg_ctx {
   std::vector<int64_t> off[6];   // batch-wide packed offsets per dg_offset_kind
   int be_prec = -1, be_nvec = 0; // last band-energy call (layout of dpsi0)
   int device = 0;
+  double* scratch = nullptr;     // this device's static scratch (no-allocation H*psi)
 
   int groups() const { return (int)g.size(); }
   int fork() {
@@ -231,6 +232,8 @@ int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* 
     b->lo = split_groups(n_elem, elems, opt);
     b->user = (hipStream_t)hip_stream;
     DG_HIP(hipGetDevice(&b->device));
+    // set-up of the no-allocation entry point: the static scratch's address on this device
+    if (int st = dg::noalloc_scratch(b->device, &b->scratch)) return st;
     const int ng = (int)b->lo.size() - 1;
     {
       // every group runs on a library stream (a capturable one even when the caller
@@ -352,6 +355,59 @@ int32_t dg_solve_elements(dg_ctx* ctx, const dg_solve_params* params, double* ei
       return dg::solve(ctx->g[i], &p, shift(eig_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)),
                        shift(resid_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)),
                        iters_host ? iters_host + a : nullptr);
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
+}
+
+int32_t dg_apply_H_noalloc(dg_ctx* ctx, int32_t elem, int32_t n_vec, int32_t prec, const void* x_dev,
+                           int64_t ldx, void* y_dev, int64_t ldy) {
+  if (!ctx) {
+    dg::set_error("ctx is NULL");
+    return DG_ERR_ARG;
+  }
+  DG_GUARD({
+    const int n_elem = ctx->lo.back();
+    if (elem < -1 || elem >= n_elem) {
+      dg::set_error("elem out of range");
+      return DG_ERR_ARG;
+    }
+    if (ldx < 0 || ldy < 0 || n_vec <= 0) {
+      dg::set_error("ldx and ldy must be >= 0 and n_vec > 0");
+      return DG_ERR_ARG;
+    }
+    // scratch: nproj x n_vec doubles per applied element, groups in disjoint parts
+    std::vector<long long> base(ctx->groups() + 1, 0);
+    for (int i = 0; i < ctx->groups(); ++i) {
+      const Ctx& c = ctx->g[i];
+      long long need = 0;
+      if (elem < 0) need = c.nproj_off[c.n_elem] * n_vec;
+      else if (elem >= ctx->lo[i] && elem < ctx->lo[i + 1])
+        need = (c.nproj_off[elem - ctx->lo[i] + 1] - c.nproj_off[elem - ctx->lo[i]]) * n_vec;
+      base[i + 1] = base[i] + (need + 31) / 32 * 32;
+    }
+    if (base.back() > dg::noalloc_scratch_doubles()) {
+      dg::set_error("the projector overlaps of this call need " + std::to_string(base.back() * 8) +
+                    " bytes, above the static scratch of " + std::to_string(dg::noalloc_scratch_doubles() * 8) +
+                    " bytes: apply fewer vectors or one element per call");
+      return DG_ERR_ARG;
+    }
+    const size_t sz = prec == DG_FP32 ? sizeof(float) : sizeof(double);
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int a = ctx->lo[i], z = ctx->lo[i + 1];
+      double* nlc = ctx->scratch + base[i];
+      if (elem >= 0) {
+        if (elem < a || elem >= z) return (int)DG_OK;
+        return dg::apply_h_noalloc(ctx->g[i], elem - a, n_vec, prec, x_dev, ldx, y_dev, ldy, nlc);
+      }
+      const int64_t nv = n_vec;
+      const int64_t ox = ldx > 0 ? (int64_t)a * ldx * nv : ctx->off[DG_OFF_GRID][a] * nv;
+      const int64_t oy = ldy > 0 ? (int64_t)a * ldy * nv : ctx->off[DG_OFF_GRID][a] * nv;
+      return dg::apply_h_noalloc(ctx->g[i], -1, n_vec, prec, shift(x_dev, ox, sz), ldx, shift(y_dev, oy, sz),
+                                 ldy, nlc);
     });
     if (st < 0) return st;
     if (int s2 = ctx->join()) return s2;

@@ -13,6 +13,9 @@
 namespace dg {
 
 constexpr int kMaxBlocks = 8;     // solver blocks per element (roles permuted per element)
+// projectors per element: the nonlocal apply stages gamma C (17 doubles per projector)
+// in 64 KB of dynamic LDS
+constexpr int kMaxProjectors = 480;
 constexpr int kExtraBlocks = 40;  // band-energy checkpoint / segment blocks (allocated on demand)
 constexpr int kTotalBlocks = kMaxBlocks + kExtraBlocks;
 enum BlockId { B_X = 0, B_W = 1, B_P = 2, B_HX = 3, B_HW = 4, B_HP = 5, B_T0 = 6, B_T1 = 7 };
@@ -76,6 +79,21 @@ struct ShapeClass {
   int max_k;
   int* elem_list_dev;              // nelem element ids
   std::vector<int> elem_list_host;
+};
+
+// Caller buffers standing in for blocks in H*psi (block ids kExtX, kExtY): the
+// no-allocation H*psi reads x and writes y in place, with the projector overlaps in
+// a caller-independent scratch array instead of the element's arena slice.
+constexpr int kExtX = -2, kExtY = -3;
+struct ExtBufs {
+  const void* x = nullptr;
+  void* y = nullptr;
+  long long ldx = 0, ldy = 0;          // > 0: element blocks ld x nvec; 0: packed (ld = N_k)
+  int nvec = 0;
+  int elem_only = -1;                  // >= 0: the buffers hold only this element's block
+  const long long* off_grid = nullptr; // per element offset of its N_k values in a packed vector
+  double* nlc = nullptr;               // projector overlaps, nproj_k x nvec per element
+  const long long* nproj_off = nullptr;  // per element prefix of nproj (its nlc block at nproj_off * nvec)
 };
 
 // kernel classes timed with HIP events when timing is enabled
@@ -145,6 +163,8 @@ struct Ctx {
   long long* dev_off_grid = nullptr;
   long long* dev_off_eig = nullptr;
   long long* dev_off_kall = nullptr;
+  long long* dev_nproj_off = nullptr;  // per element prefix of the projector counts (n_elem + 1)
+  std::vector<long long> nproj_off;    // host copy
   std::vector<int> host_ints;      // staging for small async uploads
   std::vector<int> host_ints2;      // staging of the iteration-counter reset
   std::vector<int> active_host;    // host mirror of the solver's active flags (work accounting)
@@ -195,6 +215,8 @@ const char* get_error();
 // ---- kernel launchers (k_hpsi.hip) ----
 bool grid_supported(int nx, int ny, int nz);
 int launch_hpsi(Ctx& c, int elem, int ncols, int prec, int in_blk, int out_blk, const int* active);
+// H*psi on caller buffers (ext.x -> ext.y), projector overlaps in ext.nlc
+int launch_hpsi_ext(Ctx& c, int elem, int ncols, int prec, const ExtBufs& ext);
 int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active);
 
 // ---- dense launchers (k_dense.hip) ----
@@ -264,5 +286,10 @@ int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_v
 int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv);
 int set_potential(Ctx& c, const double* v);
 int get_ritz(Ctx& c, double* theta, double* resid);
+// no-allocation H*psi (noalloc.hip): the static scratch array and its per-device address
+long long noalloc_scratch_doubles();
+int noalloc_scratch(int device, double** ptr);
+int apply_h_noalloc(Ctx& c, int elem, int n_vec, int prec, const void* x, long long ldx, void* y, long long ldy,
+                    double* nlc);
 
 }  // namespace dg

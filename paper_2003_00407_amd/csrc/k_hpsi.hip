@@ -31,7 +31,6 @@ template <>
 __device__ __forceinline__ const float* vptr<float>(const ElemDev& E) { return E.v32; }
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return (2 * k < n) ? k : k - n; }
-
 // 1/q from the hardware reciprocal (FP64: two Newton steps, a few ulps; FP32: one ulp)
 __device__ __forceinline__ double fast_recip(double q) {
   double r = __builtin_amdgcn_rcp(q);
@@ -52,6 +51,7 @@ struct PlaneArgs {
   int ncols;              // columns per element (<= 0: E.K)
   const double* theta_base;  // TFWD: per-element theta at small + vec(VS_THETA)
   int k3;                 // small-layout K3 (for theta lookup)
+  ExtBufs ext;            // caller buffers for block ids kExtX / kExtY
 };
 
 // Columns 2p and 2p+1 of a block (the second may be absent).
@@ -61,12 +61,29 @@ struct PairCols {
   T* b;
 };
 
+// First value and leading dimension of element e's columns in block blk, or in a
+// caller buffer (blk = kExtX / kExtY)
 template <typename T>
-__device__ __forceinline__ PairCols<T> pair_cols(const ElemDev& E, int blk, int pair, int ncols) {
-  T* base = reinterpret_cast<T*>(E.blk[blk]);
+__device__ __forceinline__ T* block_base(const ElemDev& E, int e, int blk, const ExtBufs& X, long long& ld) {
+  if (blk >= 0) {
+    ld = E.ld;
+    return reinterpret_cast<T*>(E.blk[blk]);
+  }
+  const long long l = blk == kExtX ? X.ldx : X.ldy;
+  T* p = reinterpret_cast<T*>(blk == kExtX ? const_cast<void*>(X.x) : X.y);
+  ld = l > 0 ? l : E.N;
+  if (X.elem_only >= 0) return p;
+  return p + (l > 0 ? (long long)e * l * X.nvec : X.off_grid[e] * X.nvec);
+}
+
+template <typename T>
+__device__ __forceinline__ PairCols<T> pair_cols(const ElemDev& E, int e, int blk, int pair, int ncols,
+                                                 const ExtBufs& X) {
+  long long ld;
+  T* base = block_base<T>(E, e, blk, X, ld);
   PairCols<T> pc;
-  pc.a = base + (size_t)(2 * pair) * E.ld;
-  pc.b = (2 * pair + 1 < ncols) ? pc.a + E.ld : nullptr;
+  pc.a = base + (size_t)(2 * pair) * ld;
+  pc.b = (2 * pair + 1 < ncols) ? pc.a + ld : nullptr;
   return pc;
 }
 
@@ -105,7 +122,7 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
   // ---- load the plane (pair) into LDS
   if constexpr (MODE == PM_HPSI || MODE == PM_TINV) {
     const int blk = (MODE == PM_HPSI) ? A.in_blk : A.out_blk;
-    PairCols<T> in = pair_cols<T>(E, blk, pair, MODE == PM_TINV ? 2 * pair + 2 : ncols);
+    PairCols<T> in = pair_cols<T>(E, e, blk, pair, MODE == PM_TINV ? 2 * pair + 2 : ncols, A.ext);
     if (zok) {
       for (int i = lt; i < NXY; i += TPP) {
         T re = in.a[zoff + i];
@@ -114,8 +131,8 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
       }
     }
   } else {  // PM_TFWD: r = HX - theta X
-    PairCols<T> xx = pair_cols<T>(E, A.in_blk, pair, ncols);
-    PairCols<T> hx = pair_cols<T>(E, A.aux_blk, pair, ncols);
+    PairCols<T> xx = pair_cols<T>(E, e, A.in_blk, pair, ncols, A.ext);
+    PairCols<T> hx = pair_cols<T>(E, e, A.aux_blk, pair, ncols, A.ext);
     const int KP = E.kmax3 + 2;
     const double* th = E.small + SmallLayout::vec(KP) + VS_THETA * KP;
     const T ta = T(th[2 * pair]);
@@ -171,7 +188,7 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
     if (xl) sfor<0, MX>([&](auto i) { P[line * PITCH + t + TL * CV(i)] = w[CV(i)]; });
     __syncthreads();
     if (zok && line < NX) {
-      PairCols<T> out = pair_cols<T>(E, A.out_blk, pair, ncols);
+      PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, ncols, A.ext);
       sfor<0, MY>([&](auto i) {
         const int y = t + TL * CV(i);
         cplx<T> r = cadd(acc[CV(i)], P[y * PITCH + line]);
@@ -194,7 +211,7 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
       cplx<T> v[MY];
       sfor<0, MY>([&](auto i) { v[CV(i)] = P[(t + TL * CV(i)) * PITCH + line]; });
       FY::forward(v, t);
-      PairCols<T> out = pair_cols<T>(E, A.out_blk, pair, 2 * pair + 2);
+      PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, 2 * pair + 2, A.ext);
       sfor<0, MY>([&](auto i) {
         const int ky = FY::freq(CV(i), t);
         out.a[zoff + ky * NX + line] = v[CV(i)].re;
@@ -217,7 +234,7 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
       cplx<T> w[MX];
       sfor<0, MX>([&](auto i) { w[CV(i)] = P[line * PITCH + FX::freq(CV(i), t)]; });
       FX::inverse(w, t);
-      PairCols<T> out = pair_cols<T>(E, A.out_blk, pair, ncols);
+      PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, ncols, A.ext);
       sfor<0, MX>([&](auto i) {
         const int x = t + TL * CV(i);
         out.a[zoff + line * NX + x] = w[CV(i)].re;
@@ -239,6 +256,7 @@ struct ZArgs {
   int in_blk, out_blk;
   int ncols;
   int k3;
+  ExtBufs ext;
 };
 
 template <typename T, int NZ, int TL, int MODE>
@@ -259,7 +277,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
 
   cplx<T> v[M];
   if constexpr (MODE == ZM_HPSI) {
-    PairCols<T> in = pair_cols<T>(E, A.in_blk, pair, ncols);
+    PairCols<T> in = pair_cols<T>(E, e, A.in_blk, pair, ncols, A.ext);
     sfor<0, M>([&](auto i) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       v[CV(i)] = {in.a[o], in.b ? in.b[o] : T(0)};
@@ -273,7 +291,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       v[CV(i)].im *= g;
     });
     FZ::inverse(v, t, wz);
-    PairCols<T> out = pair_cols<T>(E, A.out_blk, pair, ncols);
+    PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, ncols, A.ext);
     sfor<0, M>([&](auto i) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       out.a[o] += v[CV(i)].re;
@@ -281,7 +299,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
     });
   } else {
     // Teter: complex spectrum pair in W columns (2p: re, 2p+1: im), in place
-    PairCols<T> w = pair_cols<T>(E, A.out_blk, pair, 2 * pair + 2);
+    PairCols<T> w = pair_cols<T>(E, e, A.out_blk, pair, 2 * pair + 2, A.ext);
     sfor<0, M>([&](auto i) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       v[CV(i)] = {w.a[o], w.b[o]};
@@ -323,7 +341,19 @@ struct NlArgs {
   int in_blk, out_blk;
   int ncols;
   int elem_only;   // >= 0: only this element (gridDim.z == 1)
+  ExtBufs ext;
 };
+
+// projector overlaps of element e: the element's own slice (nproj x kmax3), or the
+// caller-independent scratch (nproj x nvec) of the no-allocation H*psi
+__device__ __forceinline__ double* nlc_base(const ElemDev& E, int e, const ExtBufs& X, int& ld) {
+  if (X.nlc) {
+    ld = X.nvec;
+    return X.nlc + (X.elem_only >= 0 ? 0 : X.nproj_off[e] * X.nvec);
+  }
+  ld = E.kmax3;
+  return E.nlc;
+}
 
 constexpr int kNlCols = 8;
 
@@ -341,7 +371,10 @@ __global__ void __launch_bounds__(256) k_nl_overlap(NlArgs A) {
   const int len = s1 - s0;
   const int p0 = E.grp_pbase[g], np = E.grp_pbase[g + 1] - p0;
   const long long vb = E.grp_vbase[g];
-  const T* X = reinterpret_cast<const T*>(E.blk[A.in_blk]);
+  long long ldx;
+  const T* X = block_base<T>(E, e, A.in_blk, A.ext, ldx);
+  int nld;
+  double* nlc = nlc_base(E, e, A.ext, nld);
   const T* val = nullptr;
   if constexpr (sizeof(T) == 8) val = reinterpret_cast<const T*>(E.grp_val64);
   else val = reinterpret_cast<const T*>(E.grp_val32);
@@ -358,7 +391,7 @@ __global__ void __launch_bounds__(256) k_nl_overlap(NlArgs A) {
 #pragma unroll
     for (int j = 0; j < kNlCols; ++j) {
       if (c0 + j < ncols) {
-        const T x = X[(size_t)(c0 + j) * E.ld + r];
+        const T x = X[(size_t)(c0 + j) * ldx + r];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q][j] += double(b[q]) * double(x);
       }
@@ -380,7 +413,7 @@ __global__ void __launch_bounds__(256) k_nl_overlap(NlArgs A) {
     double s = 0.0;
     for (int i = 0; i < nw; ++i) s += red[i][w];
     const int q = w / kNlCols, j = w % kNlCols;
-    if (q < np && c0 + j < ncols) E.nlc[(size_t)(p0 + q) * E.kmax3 + c0 + j] = s;
+    if (q < np && c0 + j < ncols) nlc[(size_t)(p0 + q) * nld + c0 + j] = s;
   }
 }
 
@@ -400,9 +433,11 @@ __global__ void __launch_bounds__(256) k_nl_apply(NlArgs A) {
   if (c0 >= ncols || E.nact == 0) return;
   const int nc = min(kNlApplyCols, ncols - c0);
   extern __shared__ double gc[];   // nproj x kNlApplyPitch: gamma_p C[p, c0 + j]
+  int nld;
+  const double* nlc = nlc_base(E, e, A.ext, nld);
   for (int i = threadIdx.x; i < E.nproj * kNlApplyCols; i += blockDim.x) {
     const int p = i / kNlApplyCols, j = i % kNlApplyCols;
-    gc[p * kNlApplyPitch + j] = (j < nc) ? E.gamma[p] * E.nlc[(size_t)p * E.kmax3 + c0 + j] : 0.0;
+    gc[p * kNlApplyPitch + j] = (j < nc) ? E.gamma[p] * nlc[(size_t)p * nld + c0 + j] : 0.0;
   }
   __syncthreads();
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -421,10 +456,11 @@ __global__ void __launch_bounds__(256) k_nl_apply(NlArgs A) {
 #pragma unroll
     for (int j = 0; j < kNlApplyCols; ++j) acc[j] += bv * gc[p * kNlApplyPitch + j];
   }
-  T* Y = reinterpret_cast<T*>(E.blk[A.out_blk]);
+  long long ldy;
+  T* Y = block_base<T>(E, e, A.out_blk, A.ext, ldy);
 #pragma unroll
   for (int j = 0; j < kNlApplyCols; ++j)
-    if (j < nc) Y[(size_t)(c0 + j) * E.ld + r] += T(acc[j]);
+    if (j < nc) Y[(size_t)(c0 + j) * ldy + r] += T(acc[j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -501,7 +537,8 @@ static HpsiWork hpsi_work(Ctx& c, int elem, int ncols, size_t sz, const std::vec
 }
 
 template <typename T>
-static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, const int* active) {
+static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, const int* active,
+                      const ExtBufs& ext = ExtBufs()) {
   hipStream_t s = c.stream;
   const int* act_host = (active && !c.active_host.empty()) ? c.active_host.data() : nullptr;
   const int* iota = c.iota_dev;
@@ -517,7 +554,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
   }
   // projector overlaps first (reads x only)
   {
-    NlArgs na{c.elems_dev, active, in_blk, out_blk, ncols, elem};
+    NlArgs na{c.elems_dev, active, in_blk, out_blk, ncols, elem, ext};
     int ng = 0, np = 0, kk = 0;
     for (int e = 0; e < c.n_elem; ++e) {
       if (elem >= 0 && e != elem) continue;
@@ -550,7 +587,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
       maxk = ncols > 0 ? ncols : sc.max_k;
     }
     const int npairs = (maxk + 1) / 2;
-    PlaneArgs pa{c.elems_dev, list, active, in_blk, out_blk, -1, ncols, nullptr, 0};
+    PlaneArgs pa{c.elems_dev, list, active, in_blk, out_blk, -1, ncols, nullptr, 0, ext};
     const HpsiWork hw = hpsi_work(c, elem, ncols, sizeof(T), sc.elem_list_host, act_host);
     {
       TimedScope ts(c, TC_PLANE, hw.plane);
@@ -559,7 +596,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
         return DG_ERR_SHAPE;
       }
     }
-    ZArgs za{c.elems_dev, list, active, in_blk, out_blk, ncols, 0};
+    ZArgs za{c.elems_dev, list, active, in_blk, out_blk, ncols, 0, ext};
     {
       TimedScope ts(c, TC_ZCOL, hw.zcol);
       if (!dispatch_z<T, ZM_HPSI>(sc.nz, za, sc.nx * sc.ny, npairs, nel, s)) {
@@ -569,7 +606,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
     }
   }
   if (c.nl_pending_np > 0) {
-    NlArgs na{c.elems_dev, active, in_blk, out_blk, ncols, elem};
+    NlArgs na{c.elems_dev, active, in_blk, out_blk, ncols, elem, ext};
     int nact = 0;
     for (int e = 0; e < c.n_elem; ++e)
       if (elem < 0 || e == elem) nact = std::max(nact, c.elems_host[e].nact);
@@ -586,6 +623,11 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
 int launch_hpsi(Ctx& c, int elem, int ncols, int prec, int in_blk, int out_blk, const int* active) {
   return prec == DG_FP64 ? hpsi_typed<double>(c, elem, ncols, in_blk, out_blk, active)
                          : hpsi_typed<float>(c, elem, ncols, in_blk, out_blk, active);
+}
+
+int launch_hpsi_ext(Ctx& c, int elem, int ncols, int prec, const ExtBufs& ext) {
+  return prec == DG_FP64 ? hpsi_typed<double>(c, elem, ncols, kExtX, kExtY, nullptr, ext)
+                         : hpsi_typed<float>(c, elem, ncols, kExtX, kExtY, nullptr, ext);
 }
 
 // W <- Teter(HX - X theta), three passes, for every element in place in W

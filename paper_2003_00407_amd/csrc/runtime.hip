@@ -139,7 +139,7 @@ struct Plan {
       off_de,
       off_minpiv;
   int n_extra;
-  size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_offkall, off_lists;
+  size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_offkall, off_nprojoff, off_lists;
   size_t off_ckpt, off_part;
   size_t ckpt_block_bytes;
   int n_ckpt;
@@ -197,6 +197,11 @@ static int validate(int n_elem, const dg_element_desc* d) {
     if (x.n_proj < 0 || (x.n_proj > 0 && (!x.proj_ptr || !x.proj_idx || !x.proj_val || !x.gamma))) {
       set_error("element " + std::to_string(e) + ": projector arrays missing");
       return DG_ERR_ARG;
+    }
+    if (x.n_proj > kMaxProjectors) {
+      set_error("element " + std::to_string(e) + ": " + std::to_string(x.n_proj) + " projectors, above the " +
+                std::to_string(kMaxProjectors) + " one element may carry");
+      return DG_ERR_SHAPE;
     }
     if (x.n_proj > 0) {
       if (x.proj_ptr[0] != 0) {
@@ -288,6 +293,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_offgrid = take(sizeof(long long) * (n_elem + 1));
   P.off_offeig = take(sizeof(long long) * (n_elem + 1));
   P.off_offkall = take(sizeof(long long) * (n_elem + 1));
+  P.off_nprojoff = take(sizeof(long long) * (n_elem + 1));
   P.off_lists = take(sizeof(int) * n_elem);
   size_t ckpt_block = 0;
   for (int e = 0; e < n_elem; ++e) {
@@ -528,6 +534,11 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   keep64.emplace_back(c->off_kall.begin(), c->off_kall.end());
   if ((st = cpy(P.off_offkall, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
   c->dev_off_kall = (long long*)(A + P.off_offkall);
+  c->nproj_off.assign(n_elem + 1, 0);
+  for (int e = 0; e < n_elem; ++e) c->nproj_off[e + 1] = c->nproj_off[e] + d[e].n_proj;
+  keep64.emplace_back(c->nproj_off.begin(), c->nproj_off.end());
+  if ((st = cpy(P.off_nprojoff, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
+  c->dev_nproj_off = (long long*)(A + P.off_nprojoff);
   // shape classes
   std::map<std::tuple<int, int, int>, std::vector<int>> cls;
   for (int e = 0; e < n_elem; ++e) cls[{d[e].n[0], d[e].n[1], d[e].n[2]}].push_back(e);

@@ -33,7 +33,7 @@ DG_OFF_X0, DG_OFF_VEC, DG_OFF_EIG, DG_OFF_ALB, DG_OFF_GRID, DG_OFF_KALL = range(
 
 EXPORTED = [
     "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
-    "dg_query_offsets", "dg_apply_H", "dg_solve_elements", "dg_get_ritz", "dg_get_vectors", "dg_make_alb",
+    "dg_query_offsets", "dg_apply_H", "dg_apply_H_noalloc", "dg_solve_elements", "dg_get_ritz", "dg_get_vectors", "dg_make_alb",
     "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing", "dg_timing_work",
 ]
 
@@ -71,6 +71,8 @@ _lib.dg_destroy.restype = None
 _lib.dg_query_offsets.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
 _lib.dg_apply_H.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
                             C.c_int64]
+_lib.dg_apply_H_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_int64]
 _lib.dg_get_ritz.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.dg_solve_elements.argtypes = [C.c_void_p, C.POINTER(SolveParams), C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_int32)]
@@ -206,6 +208,12 @@ class Elements:
             y = torch.empty_like(x)
         _check(_lib.dg_apply_H(self.ctx, elem, n_vec, prec, C.c_void_p(x.data_ptr()), int(ldx),
                                C.c_void_p(y.data_ptr()), int(ldy)), "dg_apply_H")
+        return y
+
+    def apply_H_noalloc(self, x, y, n_vec: int, prec: int = DG_FP64, elem: int = -1, ldx: int = 0, ldy: int = 0):
+        """y = H x in place on caller buffers, scratch in the library's static array."""
+        _check(_lib.dg_apply_H_noalloc(self.ctx, elem, n_vec, prec, C.c_void_p(x.data_ptr()), int(ldx),
+                                       C.c_void_p(y.data_ptr()), int(ldy)), "dg_apply_H_noalloc")
         return y
 
     def solve(self, x0=None, method: int = DG_LOBPCG, precision: int = DG_FP64, tol: float = 1e-8,

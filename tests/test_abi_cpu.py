@@ -85,6 +85,22 @@ def test_more_states_than_element_points_rejected():
     assert d.query_workspace([ok]) > 0
 
 
+def test_too_many_projectors_rejected():
+    import dataclasses
+    d = _lib()
+    base = W.make_config("c1").elements[0]
+    for n_p, ok in ((480, True), (481, False)):
+        el = dataclasses.replace(base, proj_ptr=np.arange(n_p + 1, dtype=np.int64),
+                                 proj_idx=np.arange(n_p, dtype=np.int32), proj_val=np.full(n_p, 0.1),
+                                 gamma=np.full(n_p, 0.01))
+        if ok:
+            assert d.query_workspace([el]) > 0
+        else:
+            with pytest.raises(d.DGError) as e:
+                d.query_workspace([el])
+            assert e.value.status == d.DG_ERR_SHAPE
+
+
 def test_non_finite_inputs_rejected():
     import dataclasses
     d = _lib()
