@@ -1901,12 +1901,14 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     }
   const int pf = prec == DG_FP64 ? (pl.maxnc + 31) / 32 : (pl.maxnc + 15) / 16;
   const int groups = pl.ntiles;
-  // row-range split: about 1024 workgroups over the launch, at least 256 rows each; the
-  // autotuner below may replace it by half or twice that for this Gram shape (the pair
-  // keeps two sets of partials)
+  // row-range split: row ranges of about 8192 rows of the largest element, and at least
+  // 2048 workgroups over the launch (long single ranges leave the launch to a tail of
+  // the largest elements), at least 256 rows each; the autotuner below may replace it
+  // by half or twice that for this Gram shape (the pair keeps two sets of partials)
   const int split_cap = std::max(1, std::min(pair ? (int)(c.gram_part_stride / (2 * part_sq)) : c.gram_max_split,
                                              rows / 256));
-  int nsplit = std::max(1, std::min(split_cap, (1024 + groups * c.n_elem - 1) / (groups * c.n_elem)));
+  int nsplit = std::max((rows + 8191) / 8192, (2048 + groups * c.n_elem - 1) / (groups * c.n_elem));
+  nsplit = std::max(1, std::min(split_cap, nsplit));
   const long long key =
       ((((((long long)prec * 1024 + maxni) * 1024 + maxnj) * 2 + sym) * 2 + (same ? 1 : 0)) * 2 + rows_e) * 2 +
       (pair ? 1 : 0);

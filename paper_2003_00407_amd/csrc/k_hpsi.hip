@@ -31,6 +31,12 @@ template <>
 __device__ __forceinline__ const float* vptr<float>(const ElemDev& E) { return E.v32; }
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return (2 * k < n) ? k : k - n; }
+// column-count code of the H*psi-family kernels for "the element's J" (<= 0 otherwise: K)
+constexpr int kNcolsJ = -2;
+
+// frequency of a first derivative: the Nyquist mode's odd derivative vanishes on the grid
+__device__ __forceinline__ int deriv_freq(int k, int n) { return (2 * k == n) ? 0 : signed_freq(k, n); }
+
 // 1/q from the hardware reciprocal (FP64: two Newton steps, a few ulps; FP32: one ulp)
 __device__ __forceinline__ double fast_recip(double q) {
   double r = __builtin_amdgcn_rcp(q);
@@ -41,7 +47,8 @@ __device__ __forceinline__ double fast_recip(double q) {
 }
 __device__ __forceinline__ float fast_recip(float q) { return __builtin_amdgcn_rcpf(q); }
 
-enum PlaneMode { PM_HPSI = 0, PM_TFWD = 1, PM_TINV = 2 };
+// HPSI: y = (T_x + T_y + V) x; TFWD/TINV: Teter passes; DX/DY: y = d/dx x, d/dy x
+enum PlaneMode { PM_HPSI = 0, PM_TFWD = 1, PM_TINV = 2, PM_DX = 3, PM_DY = 4 };
 
 struct PlaneArgs {
   const ElemDev* elems;
@@ -106,7 +113,7 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
   const int e = A.elem_list[blockIdx.z];
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
-  const int ncols = A.ncols > 0 ? A.ncols : E.K;
+  const int ncols = A.ncols > 0 ? A.ncols : (A.ncols == kNcolsJ ? E.J : E.K);
   const int pair = blockIdx.y;
   if (2 * pair >= ncols) return;
   const int slot = threadIdx.x / TPP;
@@ -120,8 +127,8 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
   cplx<T>* P = sm + (slot < PPW ? slot : 0) * NY * PITCH;
 
   // ---- load the plane (pair) into LDS
-  if constexpr (MODE == PM_HPSI || MODE == PM_TINV) {
-    const int blk = (MODE == PM_HPSI) ? A.in_blk : A.out_blk;
+  if constexpr (MODE == PM_HPSI || MODE == PM_TINV || MODE == PM_DX || MODE == PM_DY) {
+    const int blk = (MODE == PM_TINV) ? A.out_blk : A.in_blk;
     PairCols<T> in = pair_cols<T>(E, e, blk, pair, MODE == PM_TINV ? 2 * pair + 2 : ncols, A.ext);
     if (zok) {
       for (int i = lt; i < NXY; i += TPP) {
@@ -196,6 +203,44 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
         if (out.b) out.b[zoff + y * NX + line] = r.im;
       });
     }
+  } else if constexpr (MODE == PM_DX) {
+    // d/dx along the rows: multiply the spectrum by i 2 pi f / L_x (normalised by 1/NX)
+    const T g = T(sqrt(2.0 * E.kx) / NX);
+    if (zok && line < NY) {
+      cplx<T> w[MX];
+      sfor<0, MX>([&](auto i) { w[CV(i)] = P[line * PITCH + t + TL * CV(i)]; });
+      FX::forward(w, t);
+      sfor<0, MX>([&](auto i) {
+        const T m = g * T(deriv_freq(FX::freq(CV(i), t), NX));
+        w[CV(i)] = {-m * w[CV(i)].im, m * w[CV(i)].re};
+      });
+      FX::inverse(w, t);
+      PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, ncols, A.ext);
+      sfor<0, MX>([&](auto i) {
+        const int x = t + TL * CV(i);
+        out.a[zoff + line * NX + x] = w[CV(i)].re;
+        if (out.b) out.b[zoff + line * NX + x] = w[CV(i)].im;
+      });
+    }
+  } else if constexpr (MODE == PM_DY) {
+    // d/dy along the columns
+    const T g = T(sqrt(2.0 * E.ky) / NY);
+    if (zok && line < NX) {
+      cplx<T> v[MY];
+      sfor<0, MY>([&](auto i) { v[CV(i)] = P[(t + TL * CV(i)) * PITCH + line]; });
+      FY::forward(v, t);
+      sfor<0, MY>([&](auto i) {
+        const T m = g * T(deriv_freq(FY::freq(CV(i), t), NY));
+        v[CV(i)] = {-m * v[CV(i)].im, m * v[CV(i)].re};
+      });
+      FY::inverse(v, t);
+      PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, ncols, A.ext);
+      sfor<0, MY>([&](auto i) {
+        const int y = t + TL * CV(i);
+        out.a[zoff + y * NX + line] = v[CV(i)].re;
+        if (out.b) out.b[zoff + y * NX + line] = v[CV(i)].im;
+      });
+    }
   } else if constexpr (MODE == PM_TFWD) {
     // forward along x (rows), back to LDS at frequency positions, then along y
     cplx<T> w[MX];
@@ -247,7 +292,7 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
 // ---------------------------------------------------------------------------
 // z-column pass
 // ---------------------------------------------------------------------------
-enum ZMode { ZM_HPSI = 0, ZM_TETER = 1 };
+enum ZMode { ZM_HPSI = 0, ZM_TETER = 1, ZM_DZ = 2 };
 
 struct ZArgs {
   const ElemDev* elems;
@@ -266,7 +311,7 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
   const int e = A.elem_list[blockIdx.z];
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
-  const int ncols = A.ncols > 0 ? A.ncols : E.K;
+  const int ncols = A.ncols > 0 ? A.ncols : (A.ncols == kNcolsJ ? E.J : E.K);
   const int pair = blockIdx.y;
   if (2 * pair >= ncols) return;
   const int nxy = E.nx * E.ny;
@@ -296,6 +341,26 @@ __global__ void __launch_bounds__(256) k_zcol(ZArgs A) {
       const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
       out.a[o] += v[CV(i)].re;
       if (out.b) out.b[o] += v[CV(i)].im;
+    });
+  } else if constexpr (MODE == ZM_DZ) {
+    // d/dz along the columns of z
+    PairCols<T> in = pair_cols<T>(E, e, A.in_blk, pair, ncols, A.ext);
+    sfor<0, M>([&](auto i) {
+      const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
+      v[CV(i)] = {in.a[o], in.b ? in.b[o] : T(0)};
+    });
+    FZ::forward(v, t, wz);
+    const T g = T(sqrt(2.0 * E.kz) / NZ);
+    sfor<0, M>([&](auto i) {
+      const T m = g * T(deriv_freq(FZ::freq(CV(i), t), NZ));
+      v[CV(i)] = {-m * v[CV(i)].im, m * v[CV(i)].re};
+    });
+    FZ::inverse(v, t, wz);
+    PairCols<T> out = pair_cols<T>(E, e, A.out_blk, pair, ncols, A.ext);
+    sfor<0, M>([&](auto i) {
+      const size_t o = (size_t)(t + TL * CV(i)) * nxy + col;
+      out.a[o] = v[CV(i)].re;
+      if (out.b) out.b[o] = v[CV(i)].im;
     });
   } else {
     // Teter: complex spectrum pair in W columns (2p: re, 2p+1: im), in place
@@ -364,7 +429,7 @@ __global__ void __launch_bounds__(256) k_nl_overlap(NlArgs A) {
   if (A.active && !A.active[e]) return;
   const int g = blockIdx.x;
   if (g >= E.ngrp) return;
-  const int ncols = A.ncols > 0 ? A.ncols : E.K;
+  const int ncols = A.ncols > 0 ? A.ncols : (A.ncols == kNcolsJ ? E.J : E.K);
   const int c0 = blockIdx.y * kNlCols;
   if (c0 >= ncols) return;
   const int s0 = E.grp_sptr[g], s1 = E.grp_sptr[g + 1];
@@ -428,7 +493,7 @@ __global__ void __launch_bounds__(256) k_nl_apply(NlArgs A) {
   const int e = A.elem_only >= 0 ? A.elem_only : blockIdx.z;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
-  const int ncols = A.ncols > 0 ? A.ncols : E.K;
+  const int ncols = A.ncols > 0 ? A.ncols : (A.ncols == kNcolsJ ? E.J : E.K);
   const int c0 = blockIdx.y * kNlApplyCols;
   if (c0 >= ncols || E.nact == 0) return;
   const int nc = min(kNlApplyCols, ncols - c0);
@@ -654,6 +719,26 @@ static int teter_typed(Ctx& c, int x_blk, int hx_blk, int w_blk, int k3, const i
 int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active) {
   return prec == DG_FP64 ? teter_typed<double>(c, x_blk, hx_blk, w_blk, k3, active)
                          : teter_typed<float>(c, x_blk, hx_blk, w_blk, k3, active);
+}
+
+// d/dx, d/dy, d/dz of the first J_k columns of block in_blk into out blocks (FP64,
+// every element)
+int launch_gradient(Ctx& c, int in_blk, const int out_blk[3]) {
+  hipStream_t s = c.stream;
+  const int ncols = kNcolsJ;
+  for (const ShapeClass& sc : c.classes) {
+    int maxk = 0;
+    for (int e : sc.elem_list_host) maxk = std::max(maxk, c.J[e]);
+    const int npairs = (maxk + 1) / 2;
+    PlaneArgs px{c.elems_dev, sc.elem_list_dev, nullptr, in_blk, out_blk[0], -1, ncols, nullptr, 0};
+    if (!dispatch_plane<double, PM_DX>(sc.nx, px, sc.nz, npairs, sc.nelem, s)) return DG_ERR_SHAPE;
+    PlaneArgs py{c.elems_dev, sc.elem_list_dev, nullptr, in_blk, out_blk[1], -1, ncols, nullptr, 0};
+    if (!dispatch_plane<double, PM_DY>(sc.nx, py, sc.nz, npairs, sc.nelem, s)) return DG_ERR_SHAPE;
+    ZArgs zz{c.elems_dev, sc.elem_list_dev, nullptr, in_blk, out_blk[2], ncols, 0};
+    if (!dispatch_z<double, ZM_DZ>(sc.nz, zz, sc.nx * sc.ny, npairs, sc.nelem, s)) return DG_ERR_SHAPE;
+  }
+  DG_HIP(hipGetLastError());
+  return DG_OK;
 }
 
 bool grid_supported(int nx, int ny, int nz) {

@@ -269,7 +269,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
     return DG_ERR_ARG;
   }
   P.part_ld = 3 * kmax;
-  P.nsplit_max = std::max(1, std::min(64, 2048 / n_elem));
+  P.nsplit_max = std::max(1, std::min(64, 4096 / n_elem));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;

@@ -40,7 +40,7 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fullsize")
 TOL = 1e-10
 # elements whose ALB basis is stored (the angle tests); the other elements keep
 # eigenvalues, residuals, gaps and singular values only
-ALB_ELEMENTS = {"c2": (0, 5, 10), "c3": (0,), "c4": ()}
+ALB_ELEMENTS = {"c2": (0, 9, 10, 11), "c3": (0,), "c4": ()}
 
 
 def solve_element(cfg, k):

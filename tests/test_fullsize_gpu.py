@@ -12,11 +12,12 @@ What is compared:
   1e-8 Ha, for the FP64 and the mixed-precision paths (the J lowest: an eigenvalue
   missed below lambda_J would shift the comparison by a whole level);
 * ALB subspaces by their largest principal angle.  The angle is set by the gap at
-  the cut: by Davis-Kahan, each eigenvector block is within ||R|| / gap of the
-  invariant subspace, and the restriction to E_k amplifies that by at most
-  1 / sigma_min.  Where that bound is below 1e-7 the angle must be <= 1e-6 rad;
-  elsewhere (near-degenerate cuts, where the ALB span is not unique) it must stay
-  within 10x the bound.  Gaps and bounds are printed.
+  the cut: by Davis-Kahan each solution's eigenvector block lies within
+  ||R|| / gap of the invariant subspace (R the residual block: <= 1e-10 on both
+  sides here).  Where the gap is at least 1e-3 Ha that bound is below 2e-7 and the
+  ALB angle must be <= 1e-6 rad; at smaller gaps (near-degenerate cuts, where the
+  ALB span is barely determined) it must stay within 10x the bound.  Gaps, bounds
+  and the smallest singular value of the restriction are printed.
 """
 import json
 import os
@@ -124,21 +125,21 @@ def _angle_case(name, ks_all, tol_gpu):
         U = _alb_ref(name, k)
         ang = oalb.max_principal_angle(U, A[i])
         smin = min(r["sigma"])
-        bound = (float(res[i * J:(i + 1) * J].max()) + max(r["resid"][:J])) / (r["gap"] * smin)
-        print(f"{name} element {k}: ALB angle {ang:.2e} rad, gap {r['gap']:.2e} Ha, sigma_min {smin:.3f}, "
+        bound = (float(res[i * J:(i + 1) * J].max()) + max(r["resid"][:J])) / r["gap"]
+        print(f"{name} element {k}: ALB angle {ang:.2e} rad, gap {r['gap']:.2e} Ha, sigma_min {smin:.2e}, "
               f"Davis-Kahan bound {bound:.1e}", flush=True)
-        if bound <= 1e-7:
+        if r["gap"] >= 1e-3:
             n_tight += 1
             assert ang <= 1e-6
         else:
-            assert ang <= 10.0 * bound
+            assert ang <= max(1e-6, 10.0 * bound)
     return n_tight
 
 
 def test_c2_alb_subspaces():
     """Stored ALB bases of the 4x4 slab: the GPU solves those elements to 1e-10."""
     n_tight = _angle_case("c2", range(16), 1e-10)
-    print(f"{n_tight} element(s) with a Davis-Kahan bound <= 1e-7 (angle asserted <= 1e-6)")
+    print(f"{n_tight} element(s) with a gap >= 1e-3 Ha (angle asserted <= 1e-6 rad)")
 
 
 @pytest.mark.parametrize("precision", [0, 1])

@@ -37,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "Element", "Config", "make_config", "initial_block", "CONFIG_NAMES",
-    "guard_count", "honeycomb_sites", "free_electron_element",
+    "guard_count", "honeycomb_sites", "free_electron_element", "Mesh", "small_slab_with_mesh",
 ]
 
 CC_BOND = 2.68          # bohr
@@ -72,6 +72,11 @@ class Element:
     proj_val: np.ndarray
     gamma: np.ndarray
     n_atoms: int = 0
+    # global layout (slab workloads): Q_k's first grid point in the global grid (may be
+    # negative: the global grid is periodic) and a global id per projector (the same
+    # projector restricted to several extended elements carries the same id)
+    q_lo: Tuple[int, int, int] = (0, 0, 0)
+    proj_gid: Optional[np.ndarray] = None
 
     @property
     def npts(self) -> int:
@@ -98,6 +103,69 @@ class Element:
 
 
 @dataclasses.dataclass
+class Mesh:
+    """The 2D element mesh of a slab: element k = (k % n_mesh, k // n_mesh) covers the
+    global grid points [ex*elem_pts, (ex+1)*elem_pts) x [ey*elem_pts, ...) x all of z
+    (DG elements E_k; each has four faces, shared with its x and y neighbours)."""
+    n_mesh: int
+    elem_pts: int
+    global_n: Tuple[int, int, int]
+    length: Tuple[float, float, float]
+    v_global: Optional[np.ndarray] = None     # V_eff on the global grid (flat, x fastest)
+    atoms: Optional[list] = None              # per site: (ascending global flat indices, 4 x len values)
+
+    @property
+    def n_elem(self) -> int:
+        return self.n_mesh * self.n_mesh
+
+    @property
+    def elem_npts(self) -> int:
+        return self.elem_pts * self.elem_pts * self.global_n[2]
+
+    def elem_global_indices(self, k: int) -> np.ndarray:
+        """Global flat indices of E_k's points in E_k's own x-fastest order."""
+        gx, gy, gz = self.global_n
+        ox, oy, _ = self.origin(k)
+        z, y, x = np.meshgrid(np.arange(gz), np.arange(oy, oy + self.elem_pts),
+                              np.arange(ox, ox + self.elem_pts), indexing="ij")
+        return (x + gx * (y + gy * z)).ravel().astype(np.int64)
+
+    def elem_projectors(self, k: int):
+        """Every projector with support on E_k, restricted to E_k: (global ids int32,
+        CSR pointer int64, E_k-local indices int32, values float64, gamma float64).
+        Projector 4a + p is site a's s (p = 0) or p_x, p_y, p_z (p = 1, 2, 3) function."""
+        gidx = self.elem_global_indices(k)
+        loc = {int(g): i for i, g in enumerate(gidx)}
+        gids, ptr, idx, val, gam = [], [0], [], [], []
+        for a, (ai, av) in enumerate(self.atoms):
+            hit = [(loc[int(g)], t) for t, g in enumerate(ai) if int(g) in loc]
+            if not hit:
+                continue
+            hit.sort()
+            li = np.array([h[0] for h in hit], dtype=np.int32)
+            ti = np.array([h[1] for h in hit], dtype=np.int64)
+            for p in range(4):
+                gids.append(4 * a + p)
+                idx.append(li)
+                val.append(av[p][ti])
+                gam.append(GAMMA_S if p == 0 else GAMMA_P)
+                ptr.append(ptr[-1] + len(li))
+        return (np.array(gids, dtype=np.int32), np.array(ptr, dtype=np.int64),
+                np.concatenate(idx).astype(np.int32) if idx else np.zeros(0, np.int32),
+                np.concatenate(val) if val else np.zeros(0), np.array(gam, dtype=np.float64))
+
+    def origin(self, k: int) -> Tuple[int, int, int]:
+        return ((k % self.n_mesh) * self.elem_pts, (k // self.n_mesh) * self.elem_pts, 0)
+
+    def neighbours(self, k: int) -> Tuple[int, int, int, int]:
+        """Elements across the x-, x+, y-, y+ faces (periodic)."""
+        m = self.n_mesh
+        ex, ey = k % m, k // m
+        return (((ex - 1) % m) + m * ey, ((ex + 1) % m) + m * ey,
+                ex + m * ((ey - 1) % m), ex + m * ((ey + 1) % m))
+
+
+@dataclasses.dataclass
 class Config:
     name: str
     elements: List[Element]
@@ -105,6 +173,7 @@ class Config:
     x0_seed_base: int
     method: str = "lobpcg"
     precision: str = "fp64"
+    mesh: Optional[Mesh] = None
 
     @property
     def n_elem(self) -> int:
@@ -230,8 +299,9 @@ def _restrict(global_flat_idx: np.ndarray, ng, q_lo, q_n):
 
 def _slab_elements(n_mesh: int, elem_pts: int, nz: int, buffers: Sequence[int],
                    n_states: Sequence[int], vacancy_frac: float = 0.0,
-                   vacancy_seed: Optional[int] = None) -> List[Element]:
-    """Elements of a graphene-like slab on an n_mesh x n_mesh element mesh."""
+                   vacancy_seed: Optional[int] = None, mesh_out: Optional[list] = None) -> List[Element]:
+    """Elements of a graphene-like slab on an n_mesh x n_mesh element mesh (the
+    global mesh data is appended to mesh_out when given)."""
     h = H_SPACING
     ngx = n_mesh * elem_pts
     ng = (ngx, ngx, nz)
@@ -244,6 +314,8 @@ def _slab_elements(n_mesh: int, elem_pts: int, nz: int, buffers: Sequence[int],
         sites = np.delete(sites, drop, axis=0)
     vglob = _gaussian_wells(ng, length, sites, WELL_DEPTH, WELL_WIDTH).ravel()
     atoms = [_atom_projectors(ng, length, c) for c in sites]
+    if mesh_out is not None:
+        mesh_out.append(Mesh(n_mesh, elem_pts, ng, length, vglob, atoms))
     elements = []
     for k in range(n_mesh * n_mesh):
         ex, ey = k % n_mesh, k // n_mesh
@@ -257,9 +329,9 @@ def _slab_elements(n_mesh: int, elem_pts: int, nz: int, buffers: Sequence[int],
         v = vglob[(xx + ngx * (yy + ngx * zz)).ravel()]
         # atoms whose minimum-image centre lies in Q_k
         ptr = [0]
-        idx_l, val_l, gam_l = [], [], []
+        idx_l, val_l, gam_l, gid_l = [], [], [], []
         n_at = 0
-        for c, (gidx, gval) in zip(sites, atoms):
+        for a_id, (c, (gidx, gval)) in enumerate(zip(sites, atoms)):
             fx = (c[0] / h - q_lo[0]) % ngx
             fy = (c[1] / h - q_lo[1]) % ngx
             if not (fx < nq and fy < nq):
@@ -273,6 +345,7 @@ def _slab_elements(n_mesh: int, elem_pts: int, nz: int, buffers: Sequence[int],
                 idx_l.append(loc.astype(np.int32))
                 val_l.append(gval[p][keep][order])
                 gam_l.append(GAMMA_S if p == 0 else GAMMA_P)
+                gid_l.append(4 * a_id + p)
                 ptr.append(ptr[-1] + len(loc))
         elements.append(Element(
             n=(nq, nq, nz), length=(nq * h, nq * h, nz * h),
@@ -281,8 +354,12 @@ def _slab_elements(n_mesh: int, elem_pts: int, nz: int, buffers: Sequence[int],
             proj_ptr=np.array(ptr, dtype=np.int64),
             proj_idx=(np.concatenate(idx_l) if idx_l else np.zeros(0, np.int32)).astype(np.int32),
             proj_val=(np.concatenate(val_l) if val_l else np.zeros(0)).astype(np.float64),
-            gamma=np.array(gam_l, dtype=np.float64), n_atoms=n_at))
+            gamma=np.array(gam_l, dtype=np.float64), n_atoms=n_at,
+            q_lo=q_lo, proj_gid=np.array(gid_l, dtype=np.int32)))
     return elements
+
+
+
 
 
 def _box_element(n: Tuple[int, int, int], length: Tuple[float, float, float], sites,
@@ -307,6 +384,14 @@ def small_slab(n_mesh=3, elem_pts=8, nz=32, buffer=4, n_states=8) -> List[Elemen
                           [n_states] * (n_mesh * n_mesh))
 
 
+def small_slab_with_mesh(n_mesh=3, elem_pts=8, nz=32, buffer=4, n_states=8):
+    """small_slab's elements and their global mesh (DG element layout, V, projectors)."""
+    out: list = []
+    els = _slab_elements(n_mesh, elem_pts, nz, [buffer] * (n_mesh * n_mesh), [n_states] * (n_mesh * n_mesh),
+                         mesh_out=out)
+    return els, out[0]
+
+
 CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
 
 
@@ -319,26 +404,27 @@ def make_config(name: str) -> Config:
         el = _box_element((16, 16, 16), (10.0, 10.0, 10.0), sites, 8)
         return Config("c1", [el], "single 10 bohr cubic element, 16^3 grid, 4 Gaussian wells, "
                       "no projectors, 8 states, FP64 LOBPCG", 100, "lobpcg", "fp64")
+    mo: list = []
     if name in ("c2", "c5"):
-        els = _slab_elements(4, 16, 64, [16] * 16, [40] * 16)
+        els = _slab_elements(4, 16, 64, [16] * 16, [40] * 16, mesh_out=mo)
         desc = ("graphene-like slab, 4x4 elements of 16x16x64, extended elements 48x48x64 "
                 "(h = 0.4 bohr), Gaussian wells + 4 projectors per site, 40 states per element")
         if name == "c2":
-            return Config("c2", els, desc + ", FP64", 1000, "lobpcg", "fp64")
+            return Config("c2", els, desc + ", FP64", 1000, "lobpcg", "fp64", mo[0])
         return Config("c5", els, desc + ", band energy through a degree-16 Chebyshev filter",
-                      1000, "chfsi", "fp64")
+                      1000, "chfsi", "fp64", mo[0])
     if name == "c3":
-        els = _slab_elements(8, 16, 64, [16] * 64, [60] * 64)
+        els = _slab_elements(8, 16, 64, [16] * 64, [60] * 64, mesh_out=mo)
         return Config("c3", els, "graphene-like slab, 8x8 elements, extended 48x48x64, "
-                      "60 states per element, mixed precision", 3000, "lobpcg", "mixed")
+                      "60 states per element, mixed precision", 3000, "lobpcg", "mixed", mo[0])
     if name == "c4":
         rng = np.random.default_rng(4)
         q = rng.choice([32, 48, 64], size=256)
         js = rng.integers(20, 81, size=256)
         els = _slab_elements(16, 16, 64, [(int(x) - 16) // 2 for x in q], js,
-                             vacancy_frac=0.02, vacancy_seed=44)
+                             vacancy_frac=0.02, vacancy_seed=44, mesh_out=mo)
         return Config("c4", els, "uneven batch: 256 elements, extended in-plane 32/48/64 x 64, "
-                      "20-80 states, 2% vacancies, mixed precision", 4000, "lobpcg", "mixed")
+                      "20-80 states, 2% vacancies, mixed precision", 4000, "lobpcg", "mixed", mo[0])
     raise ValueError(f"unknown config {name!r}")
 
 
