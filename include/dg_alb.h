@@ -138,7 +138,9 @@ enum dg_offset_kind {
   DG_OFF_EIG = 2,  /* J_k values per element (eigenvalues, residuals)    */
   DG_OFF_ALB = 3,  /* packed |E_k| x J_k blocks (dg_make_alb)            */
   DG_OFF_GRID = 4, /* N_k values per element (V, dE/dV)                  */
-  DG_OFF_KALL = 5  /* J_k+g_k values per element                         */
+  DG_OFF_KALL = 5, /* J_k+g_k values per element                         */
+  DG_OFF_ELEM = 6, /* |E_k| values per element (density)                 */
+  DG_OFF_JJ = 7    /* J_k x J_k blocks (density-matrix diagonal blocks)   */
 };
 
 /* Human-readable name of a status code (static string). */
@@ -230,6 +232,54 @@ int32_t dg_get_vectors(dg_ctx *ctx, double *x_dev);
  * (sigma_min <= 1e-10 sigma_max, or the orthonormalisation breaks down): the
  * outputs are then not valid. */
 int32_t dg_make_alb(dg_ctx *ctx, double *alb_dev, double *sval_dev);
+
+/* The element mesh of the global problem, for the DG Hamiltonian (Eq. (7),
+ * DGHamiltonian).  The context's elements, in order, are the elements E_k of an
+ * n_mesh[0] x n_mesh[1] periodic 2D mesh (element k at (k % n_mesh[0],
+ * k / n_mesh[0])); each spans the whole periodic z range and shares its x and y
+ * faces with its neighbours, which must have the same E_k extent along the face.
+ * Projectors: every projector b_{I,l} with support on E_k, restricted to E_k,
+ * with a global id that identifies the same projector in other elements. */
+typedef struct {
+  int32_t n_mesh[2];         /* elements along x and y, >= 3 each                        */
+  double alpha;              /* interior-penalty parameter (Ha bohr)                     */
+  const int32_t *proj_count; /* per element: projectors with support on E_k               */
+  const int32_t *proj_gid;   /* their global ids, the elements' lists concatenated        */
+  const int64_t *proj_ptr;   /* sum(proj_count) + 1 offsets into proj_idx / proj_val       */
+  const int32_t *proj_idx;   /* E_k-local grid indices (x fastest inside E_k), ascending   */
+  const double *proj_val;    /* values on E_k (the global projector's, unnormalised)       */
+  const double *gamma;       /* per projector weight (Ha)                                 */
+} dg_mesh_desc;
+
+/* Block-sparse layout of H^DG for dg_build_hamiltonian: row k holds the blocks
+ * (k, col_idx[b]) for b in [row_ptr[k], row_ptr[k+1]), the distinct elements that
+ * are k itself, share a face with it, or share a projector with it, in ascending
+ * order; block b is J_k x J_col column-major (ld J_k) at block_off[b] doubles
+ * (n_blocks + 1 values, last = total).  Call with row_ptr = col_idx = block_off =
+ * NULL to get *n_blocks and *work_bytes (the device workspace of the build), then
+ * with arrays of n_elem + 1, n_blocks and n_blocks + 1 values.  CPU only (host mesh
+ * data is read).  Errors: DG_ERR_ARG, DG_ERR_SHAPE. */
+int32_t dg_query_hamiltonian(const dg_ctx *ctx, const dg_mesh_desc *mesh, int32_t *n_blocks, int64_t *row_ptr,
+                             int32_t *col_idx, int64_t *block_off, size_t *work_bytes);
+
+/* The DG Hamiltonian H^DG (Eq. (7)) in the ALB basis of the last solve: per
+ * element the kinetic and local-potential block 1/2 <grad phi, grad phi'> +
+ * <phi, V phi'> over E_k; the nonlocal coupling sum gamma <phi, b><b, phi'> of
+ * every pair of elements sharing a projector; and the interior-penalty face terms
+ * -1/2 <[[phi]], {{grad phi'}}> - 1/2 <{{grad phi}}, [[phi']]> + alpha <[[phi]],
+ * [[phi']]> of the four faces of every element.  ALBs are the orthonormal bases
+ * of dg_make_alb; inside E_k and on its faces they are evaluated as the
+ * trigonometric polynomials on Q_k whose restriction they are (gradients by the
+ * spectral derivative on Q_k, traces by trigonometric interpolation half a grid
+ * step beyond E_k's outer points); element and face integrals are rectangle sums
+ * of the Euclidean-normalised grid functions (a face sum carries 1 / h_normal).
+ * hdg_dev: the blocks (dg_query_hamiltonian); work_dev: work_bytes of device
+ * scratch (256-byte aligned).  Uses the solver's work blocks (call dg_make_alb or
+ * dg_get_vectors before it if needed; X stays for warm starts).  Errors:
+ * DG_ERR_STATE before a solve, DG_ERR_ARG, DG_ERR_SHAPE (mesh does not match the
+ * elements), DG_ERR_NUMERIC (rank-deficient restriction), DG_ERR_HIP. */
+int32_t dg_build_hamiltonian(dg_ctx *ctx, const dg_mesh_desc *mesh, double *hdg_dev, void *work_dev,
+                             size_t work_bytes);
 
 /* Band energy E = sum_i f_i psi_i^T H psi_i with Psi = p_m(H) Psi_0, p_m the
  * degree-m scaled Chebyshev filter of Algorithm 2 / Eq. (8) with bounds

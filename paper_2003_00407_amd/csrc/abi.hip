@@ -77,7 +77,7 @@ struct dg_ctx {
   std::vector<hipStream_t> own;  // library streams, one per group
   hipEvent_t fork_ev = nullptr;
   std::vector<hipEvent_t> join_ev;
-  std::vector<int64_t> off[6];   // batch-wide packed offsets per dg_offset_kind
+  std::vector<int64_t> off[8];   // batch-wide packed offsets per dg_offset_kind
   int be_prec = -1, be_nvec = 0; // last band-energy call (layout of dpsi0)
   int device = 0;
   double* scratch = nullptr;     // this device's static scratch (no-allocation H*psi)
@@ -120,6 +120,8 @@ const std::vector<int64_t>& group_off(const Ctx& c, int kind) {
     case DG_OFF_EIG: return c.off_eig;
     case DG_OFF_ALB: return c.off_alb;
     case DG_OFF_GRID: return c.off_grid;
+    case DG_OFF_ELEM: return c.off_elem;
+    case DG_OFF_JJ: return c.off_jj;
     default: return c.off_kall;
   }
 }
@@ -273,7 +275,7 @@ int32_t dg_create_elements(dg_ctx** ctx, int32_t n_elem, const dg_element_desc* 
       used += round256(need);
     }
     // batch-wide offsets: the groups' packed buffers follow each other
-    for (int kind = 0; kind < 6; ++kind) {
+    for (int kind = 0; kind < 8; ++kind) {
       std::vector<int64_t>& o = b->off[kind];
       o.assign(1, 0);
       for (int i = 0; i < ng; ++i) {
@@ -295,7 +297,7 @@ int32_t dg_query_offsets(const dg_ctx* ctx, int32_t kind, int64_t* offsets) {
     dg::set_error("ctx or offsets is NULL");
     return DG_ERR_ARG;
   }
-  if (kind < 0 || kind > 5) {
+  if (kind < 0 || kind > 7) {
     dg::set_error("unknown offset kind");
     return DG_ERR_ARG;
   }
@@ -412,6 +414,130 @@ int32_t dg_apply_H_noalloc(dg_ctx* ctx, int32_t elem, int32_t n_vec, int32_t pre
     if (st < 0) return st;
     if (int s2 = ctx->join()) return s2;
     return st;
+  })
+}
+
+}  // extern "C"
+
+namespace {
+
+int dg_mesh_info(const dg_ctx* ctx, const dg_mesh_desc* m, dg::DgMeshInfo& mi, std::vector<dg::DgElemShape>& sh) {
+  if (!ctx || !m || !m->proj_count || (!m->proj_ptr)) {
+    dg::set_error("ctx or mesh (or its projector arrays) is NULL");
+    return DG_ERR_ARG;
+  }
+  const int M = ctx->lo.back();
+  mi.n_mesh[0] = m->n_mesh[0];
+  mi.n_mesh[1] = m->n_mesh[1];
+  mi.alpha = m->alpha;
+  mi.count = m->proj_count;
+  mi.gid = m->proj_gid;
+  mi.ptr = reinterpret_cast<const long long*>(m->proj_ptr);
+  mi.idx = m->proj_idx;
+  mi.val = m->proj_val;
+  mi.gamma = m->gamma;
+  mi.pbase.assign(M + 1, 0);
+  for (int k = 0; k < M; ++k) {
+    if (m->proj_count[k] < 0) {
+      dg::set_error("negative projector count");
+      return DG_ERR_ARG;
+    }
+    mi.pbase[k + 1] = mi.pbase[k] + m->proj_count[k];
+  }
+  if (mi.pbase[M] > 0 && (!m->proj_gid || !m->proj_idx || !m->proj_val || !m->gamma)) {
+    dg::set_error("projector arrays missing");
+    return DG_ERR_ARG;
+  }
+  for (int p = 0; p < mi.pbase[M]; ++p)
+    if (mi.ptr[p + 1] < mi.ptr[p]) {
+      dg::set_error("proj_ptr not monotone");
+      return DG_ERR_ARG;
+    }
+  if (!(m->alpha >= 0.0)) {
+    dg::set_error("alpha must be >= 0");
+    return DG_ERR_ARG;
+  }
+  sh.resize(M);
+  for (int i = 0; i < ctx->groups(); ++i) {
+    const Ctx& c = ctx->g[i];
+    for (int e = 0; e < c.n_elem; ++e) {
+      dg::DgElemShape& a = sh[ctx->lo[i] + e];
+      a.J = c.J[e];
+      for (int q = 0; q < 3; ++q) {
+        a.n[q] = c.nxyz[q][e];
+        a.len[q] = c.lens[q][e];
+        a.elo[q] = c.elo[q][e];
+        a.en[q] = c.en[q][e];
+      }
+    }
+  }
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dg_query_hamiltonian(const dg_ctx* ctx, const dg_mesh_desc* mesh, int32_t* n_blocks, int64_t* row_ptr,
+                             int32_t* col_idx, int64_t* block_off, size_t* work_bytes) {
+  DG_GUARD({
+    dg::DgMeshInfo mi;
+    std::vector<dg::DgElemShape> sh;
+    if (int st = dg_mesh_info(ctx, mesh, mi, sh)) return st;
+    dg::DgPlan P;
+    if (int st = dg::dg_plan(mi, sh, P)) return st;
+    if (n_blocks) *n_blocks = (int32_t)P.blk.size();
+    if (row_ptr)
+      for (size_t i = 0; i < P.row_ptr.size(); ++i) row_ptr[i] = P.row_ptr[i];
+    if (col_idx)
+      for (size_t b = 0; b < P.blk.size(); ++b) col_idx[b] = P.blk[b].nb;
+    if (block_off) {
+      for (size_t b = 0; b < P.blk.size(); ++b) block_off[b] = P.blk[b].off;
+      block_off[P.blk.size()] = P.total_values;
+    }
+    if (work_bytes) *work_bytes = (size_t)P.total_doubles * sizeof(double);
+    return DG_OK;
+  })
+}
+
+int32_t dg_build_hamiltonian(dg_ctx* ctx, const dg_mesh_desc* mesh, double* hdg_dev, void* work_dev,
+                             size_t work_bytes) {
+  DG_GUARD({
+    dg::DgMeshInfo mi;
+    std::vector<dg::DgElemShape> sh;
+    if (int st = dg_mesh_info(ctx, mesh, mi, sh)) return st;
+    if (!hdg_dev || !work_dev || ((uintptr_t)work_dev & 255)) {
+      dg::set_error("hdg_dev and work_dev must be non-NULL, work_dev 256-byte aligned");
+      return DG_ERR_ARG;
+    }
+    dg::DgPlan P;
+    if (int st = dg::dg_plan(mi, sh, P)) return st;
+    if (work_bytes < (size_t)P.total_doubles * sizeof(double)) {
+      dg::set_error("work buffer too small: need " + std::to_string(P.total_doubles * 8) + " bytes");
+      return DG_ERR_OOM;
+    }
+    for (const Ctx& c : ctx->g)
+      if (!c.solved) {
+        dg::set_error("no solve has completed on this context");
+        return DG_ERR_STATE;
+      }
+    double* work = static_cast<double*>(work_dev);
+    std::vector<std::vector<char>> keep;
+    if (int st = dg::dg_upload(ctx->user, mi, sh, P, work, keep)) return st;
+    if (int st = ctx->fork()) return st;
+    const dg::DgElem* del = reinterpret_cast<const dg::DgElem*>(work + P.off_del);
+    int st = each_group(ctx, [&](int i) {
+      Ctx& c = ctx->g[i];
+      c.dg_sval_off = P.off_sval + ctx->off[DG_OFF_EIG][ctx->lo[i]];
+      c.dg_max_np = 0;
+      for (int k = ctx->lo[i]; k < ctx->lo[i + 1]; ++k) c.dg_max_np = std::max(c.dg_max_np, mi.count[k]);
+      return dg::dg_element_terms(c, work, del);
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    if (int s3 = dg::dg_assemble(ctx->user, P, work, hdg_dev, mi.alpha)) return s3;
+    DG_HIP(hipStreamSynchronize(ctx->user));
+    return DG_OK;
   })
 }
 

@@ -96,6 +96,56 @@ struct ExtBufs {
   const long long* nproj_off = nullptr;  // per element prefix of nproj (its nlc block at nproj_off * nvec)
 };
 
+// DG Hamiltonian (dg.hip): per element data in the caller's work buffer (offsets in
+// doubles), indexed by the element's position in the whole batch
+struct DgElem {
+  int J, np;              // ALBs, projectors with support on E_k
+  int en[3];              // E_k extent
+  int npts[4];            // points of the faces x-, x+, y-, y+
+  double inv_h[2];        // 1 / h_x, 1 / h_y
+  long long l_off;        // local block (kinetic + V), J x J column-major
+  long long tr_off;       // traces: per face, J values then J outward derivatives, npts each
+  long long ovl_off;      // projector overlaps, np x J
+  long long w_off;        // face weights: 4 faces x {value, derivative} x 64
+  long long pj_off;       // projector CSR pointer (np + 1, int64)
+  long long pidx_off;     // E_k-local indices (int32)
+  long long pval_off;     // values (gamma: the np doubles just before)
+};
+struct DgMeshInfo {
+  int n_mesh[2];
+  double alpha;
+  const int* count;
+  const int* gid;
+  const long long* ptr;
+  const int* idx;
+  const double* val;
+  const double* gamma;
+  std::vector<int> pbase;  // prefix of count (n_elem + 1)
+};
+struct DgElemShape {
+  int J;
+  int n[3], elo[3], en[3];
+  double len[3];
+};
+// one block (k, nb) of H^DG: its place in the output and what contributes to it
+struct DgBlock {
+  int k, nb;
+  int face;               // -1: no common face; 0..3: the face of k shared with nb; 4: nb = k
+  int pair_lo, pair_hi;   // shared projectors (pairs of local indices) in the pair list
+  long long off;          // first value in the output (doubles)
+};
+struct DgPlan {
+  std::vector<DgElem> el;
+  std::vector<DgBlock> blk;
+  std::vector<long long> row_ptr;
+  std::vector<int> pairs;
+  long long off_del = 0, off_blk = 0, off_pairs = 0, off_sval = 0;
+  long long total_doubles = 0, total_values = 0;
+};
+int dg_plan(const DgMeshInfo& mi, const std::vector<DgElemShape>& sh, DgPlan& P);
+int dg_upload(hipStream_t s, const DgMeshInfo& mi, const std::vector<DgElemShape>& sh, const DgPlan& P,
+              double* work, std::vector<std::vector<char>>& keep);
+
 // kernel classes timed with HIP events when timing is enabled
 enum TimeClass { TC_PLANE = 0, TC_ZCOL = 1, TC_NL = 2, TC_TETER = 3, TC_GRAM = 4, TC_ROT = 5, TC_RR = 6,
                  TC_OTHER = 7, TC_N = 8 };
@@ -120,13 +170,17 @@ struct Ctx {
   std::vector<ShapeClass> classes;
   std::vector<int> J, G, K, N, ld;
   std::vector<int> elo[3], en[3];
-  std::vector<int64_t> off_x0, off_vec, off_eig, off_alb, off_grid, off_kall;
+  std::vector<int64_t> off_x0, off_vec, off_eig, off_alb, off_grid, off_kall, off_elem, off_jj;
   char* arena = nullptr;
   size_t arena_bytes = 0, arena_used = 0;
   bool solved = false;             // the blocks hold a solution (ALBs, vectors may be taken)
   bool have_x = false;             // X (with guards) of the last solve is intact: warm start possible
   int elem_base = 0;               // index of this group's first element in the whole batch
   int last_breakdowns = 0;         // Rayleigh-Ritz breakdowns of the X block in the last stage
+  std::vector<int> nxyz[3];        // Q_k grid per element
+  std::vector<double> lens[3];     // Q_k box lengths per element
+  long long dg_sval_off = 0;       // DG build: this group's singular-value scratch in the work buffer
+  int dg_max_np = 0;               // DG build: most projectors on one E_k of this group
   int solved_K3 = 0;
   // band-energy state
   int be_degree = 0, be_prec = 0, be_nvec = 0, be_stride = 1, be_nckpt = 0;
@@ -163,6 +217,8 @@ struct Ctx {
   long long* dev_off_grid = nullptr;
   long long* dev_off_eig = nullptr;
   long long* dev_off_kall = nullptr;
+  long long* dev_off_elem = nullptr;
+  long long* dev_off_jj = nullptr;
   long long* dev_nproj_off = nullptr;  // per element prefix of the projector counts (n_elem + 1)
   std::vector<long long> nproj_off;    // host copy
   std::vector<int> host_ints;      // staging for small async uploads
@@ -286,6 +342,8 @@ int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_v
 int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv);
 int set_potential(Ctx& c, const double* v);
 int get_ritz(Ctx& c, double* theta, double* resid);
+int dg_element_terms(Ctx& c, double* work, const DgElem* del_dev);
+int dg_assemble(hipStream_t s, const DgPlan& P, double* work, double* hdg, double alpha);
 // no-allocation H*psi (noalloc.hip): the static scratch array and its per-device address
 long long noalloc_scratch_doubles();
 int noalloc_scratch(int device, double** ptr);

@@ -139,7 +139,8 @@ struct Plan {
       off_de,
       off_minpiv;
   int n_extra;
-  size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_offkall, off_nprojoff, off_lists;
+  size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_offkall, off_offelem, off_offjj,
+      off_nprojoff, off_lists;
   size_t off_ckpt, off_part;
   size_t ckpt_block_bytes;
   int n_ckpt;
@@ -293,6 +294,8 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_offgrid = take(sizeof(long long) * (n_elem + 1));
   P.off_offeig = take(sizeof(long long) * (n_elem + 1));
   P.off_offkall = take(sizeof(long long) * (n_elem + 1));
+  P.off_offelem = take(sizeof(long long) * (n_elem + 1));
+  P.off_offjj = take(sizeof(long long) * (n_elem + 1));
   P.off_nprojoff = take(sizeof(long long) * (n_elem + 1));
   P.off_lists = take(sizeof(int) * n_elem);
   size_t ckpt_block = 0;
@@ -400,6 +403,8 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   for (int a = 0; a < 3; ++a) {
     c->elo[a].resize(n_elem);
     c->en[a].resize(n_elem);
+    c->nxyz[a].resize(n_elem);
+    c->lens[a].resize(n_elem);
   }
   // host staging buffers kept alive until the stream synchronises below
   std::vector<std::vector<float>> keep32;
@@ -423,6 +428,8 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
       E.en[a] = x.elem_n[a];
       c->elo[a][e] = x.elem_lo[a];
       c->en[a][e] = x.elem_n[a];
+      c->nxyz[a][e] = x.n[a];
+      c->lens[a][e] = x.len[a];
     }
     const double tp = 2.0 * M_PI;
     E.kx = 0.5 * (tp / x.len[0]) * (tp / x.len[0]);
@@ -507,6 +514,8 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->off_alb.assign(n_elem + 1, 0);
   c->off_grid.assign(n_elem + 1, 0);
   c->off_kall.assign(n_elem + 1, 0);
+  c->off_elem.assign(n_elem + 1, 0);
+  c->off_jj.assign(n_elem + 1, 0);
   for (int e = 0; e < n_elem; ++e) {
     const int en = c->en[0][e] * c->en[1][e] * c->en[2][e];
     c->off_x0[e + 1] = c->off_x0[e] + (int64_t)c->N[e] * c->K[e];
@@ -515,6 +524,8 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
     c->off_alb[e + 1] = c->off_alb[e] + (int64_t)en * c->J[e];
     c->off_grid[e + 1] = c->off_grid[e] + c->N[e];
     c->off_kall[e + 1] = c->off_kall[e] + c->K[e];
+    c->off_elem[e + 1] = c->off_elem[e] + en;
+    c->off_jj[e + 1] = c->off_jj[e] + (int64_t)c->J[e] * c->J[e];
   }
   keep64.emplace_back(c->off_x0.begin(), c->off_x0.end());
   if ((st = cpy(P.off_offx0, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
@@ -534,6 +545,12 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   keep64.emplace_back(c->off_kall.begin(), c->off_kall.end());
   if ((st = cpy(P.off_offkall, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
   c->dev_off_kall = (long long*)(A + P.off_offkall);
+  keep64.emplace_back(c->off_elem.begin(), c->off_elem.end());
+  if ((st = cpy(P.off_offelem, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
+  c->dev_off_elem = (long long*)(A + P.off_offelem);
+  keep64.emplace_back(c->off_jj.begin(), c->off_jj.end());
+  if ((st = cpy(P.off_offjj, keep64.back().data(), sizeof(long long) * (n_elem + 1)))) return st;
+  c->dev_off_jj = (long long*)(A + P.off_offjj);
   c->nproj_off.assign(n_elem + 1, 0);
   for (int e = 0; e < n_elem; ++e) c->nproj_off[e + 1] = c->nproj_off[e] + d[e].n_proj;
   keep64.emplace_back(c->nproj_off.begin(), c->nproj_off.end());

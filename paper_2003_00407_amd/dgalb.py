@@ -35,6 +35,7 @@ EXPORTED = [
     "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
     "dg_query_offsets", "dg_apply_H", "dg_apply_H_noalloc", "dg_solve_elements", "dg_get_ritz", "dg_get_vectors", "dg_make_alb",
     "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing", "dg_timing_work",
+    "dg_query_hamiltonian", "dg_build_hamiltonian",
 ]
 
 
@@ -57,6 +58,13 @@ class SolveParams(C.Structure):
                 ("tol_mixed", C.c_double), ("max_iter", C.c_int32), ("cheb_degree", C.c_int32),
                 ("x0_dev", C.c_void_p), ("graph_iters", C.c_int32), ("seed", C.c_int64),
                 ("warm_start", C.c_int32)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_mesh", C.c_int32 * 2), ("alpha", C.c_double), ("proj_count", C.POINTER(C.c_int32)),
+                ("proj_gid", C.POINTER(C.c_int32)), ("proj_ptr", C.POINTER(C.c_int64)),
+                ("proj_idx", C.POINTER(C.c_int32)), ("proj_val", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double))]
 
 
 _lib.dg_status_string.restype = C.c_char_p
@@ -84,6 +92,9 @@ _lib.dg_band_energy_backward.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_
 _lib.dg_set_potential.argtypes = [C.c_void_p, C.c_void_p]
 _lib.dg_timing.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.dg_timing_work.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+_lib.dg_query_hamiltonian.argtypes = [C.c_void_p, C.POINTER(MeshDesc), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
+_lib.dg_build_hamiltonian.argtypes = [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.c_void_p, C.c_size_t]
 
 
 class DGError(RuntimeError):
@@ -148,6 +159,34 @@ def query_workspace(elements: Sequence, n_guard: int = -1, max_cheb_degree: int 
     out = C.c_size_t(0)
     _check(_lib.dg_query_workspace(hd.n, hd.arr, C.byref(opt), C.byref(out)), "dg_query_workspace")
     return int(out.value)
+
+
+class HostMesh:
+    """ctypes mesh descriptor (dg_mesh_desc) from per-element projector lists on E_k
+    [(global ids, CSR pointer, E_k-local indices, values, gamma), ...] (keeps the arrays)."""
+
+    def __init__(self, n_mesh, alpha: float, projectors):
+        counts = np.array([len(p[0]) for p in projectors], dtype=np.int32)
+        gid = np.ascontiguousarray(np.concatenate([p[0] for p in projectors]).astype(np.int32))
+        ptr, base = [np.zeros(1, np.int64)], 0
+        for p in projectors:
+            ptr.append(p[1][1:].astype(np.int64) + base)
+            base += int(p[1][-1])
+        ptr = np.ascontiguousarray(np.concatenate(ptr))
+        idx = np.ascontiguousarray(np.concatenate([p[2] for p in projectors]).astype(np.int32))
+        val = np.ascontiguousarray(np.concatenate([p[3] for p in projectors]).astype(np.float64))
+        gam = np.ascontiguousarray(np.concatenate([p[4] for p in projectors]).astype(np.float64))
+        self.keep = [counts, gid, ptr, idx, val, gam]
+        d = MeshDesc()
+        d.n_mesh[:] = [int(n_mesh[0]), int(n_mesh[1])]
+        d.alpha = float(alpha)
+        d.proj_count = _ptr(counts, C.c_int32)
+        d.proj_gid = _ptr(gid, C.c_int32)
+        d.proj_ptr = _ptr(ptr, C.c_int64)
+        d.proj_idx = _ptr(idx, C.c_int32)
+        d.proj_val = _ptr(val, C.c_double)
+        d.gamma = _ptr(gam, C.c_double)
+        self.desc = d
 
 
 class Elements:
@@ -293,6 +332,46 @@ class Elements:
         _check(_lib.dg_band_energy_backward(self.ctx, _ptr(de, C.c_double), C.c_void_p(dpsi.data_ptr()),
                                             C.c_void_p(dv.data_ptr())), "dg_band_energy_backward")
         return dpsi, dv
+
+    def hamiltonian_layout(self, hmesh: "HostMesh"):
+        """Block-sparse layout of the DG Hamiltonian for this mesh: (row_ptr (n_elem + 1),
+        col_idx (n_blocks), block_off (n_blocks + 1), work bytes)."""
+        nb = C.c_int32(0)
+        wb = C.c_size_t(0)
+        _check(_lib.dg_query_hamiltonian(self.ctx, C.byref(hmesh.desc), C.byref(nb), None, None, None, C.byref(wb)),
+               "dg_query_hamiltonian")
+        row_ptr = np.zeros(self.n_elem + 1, dtype=np.int64)
+        col = np.zeros(nb.value, dtype=np.int32)
+        off = np.zeros(nb.value + 1, dtype=np.int64)
+        _check(_lib.dg_query_hamiltonian(self.ctx, C.byref(hmesh.desc), C.byref(nb), _ptr(row_ptr, C.c_int64),
+                                         _ptr(col, C.c_int32), _ptr(off, C.c_int64), C.byref(wb)),
+               "dg_query_hamiltonian")
+        return row_ptr, col, off, int(wb.value)
+
+    def build_hamiltonian(self, hmesh: "HostMesh"):
+        """H^DG (packed FP64 device tensor of blocks) and its layout (row_ptr, col_idx,
+        block_off); block b of row k is J_k x J_col column-major; see dg_build_hamiltonian."""
+        torch = self.torch
+        row_ptr, col, off, wb = self.hamiltonian_layout(hmesh)
+        H = self._dev(int(off[-1]), torch.float64)
+        work = torch.empty(wb + 256, dtype=torch.uint8, device=self.device)
+        wp = (work.data_ptr() + 255) // 256 * 256
+        self.generation += 1
+        _check(_lib.dg_build_hamiltonian(self.ctx, C.byref(hmesh.desc), C.c_void_p(H.data_ptr()), C.c_void_p(wp),
+                                         C.c_size_t(wb)), "dg_build_hamiltonian")
+        return H, (row_ptr, col, off)
+
+    def hamiltonian_blocks(self, H, layout) -> dict:
+        """{(k, nb): J_k x J_nb numpy block} from build_hamiltonian's output (host copy)."""
+        row_ptr, col, off = layout
+        Hh = H.cpu().numpy()
+        Js = [e.n_states for e in self.elements]
+        out = {}
+        for k in range(self.n_elem):
+            for b in range(int(row_ptr[k]), int(row_ptr[k + 1])):
+                nb = int(col[b])
+                out[(k, nb)] = Hh[off[b]:off[b + 1]].reshape(Js[nb], Js[k]).T
+        return out
 
     TIMING_CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
 
