@@ -281,6 +281,22 @@ int32_t dg_query_hamiltonian(const dg_ctx *ctx, const dg_mesh_desc *mesh, int32_
 int32_t dg_build_hamiltonian(dg_ctx *ctx, const dg_mesh_desc *mesh, double *hdg_dev, void *work_dev,
                              size_t work_bytes);
 
+/* Electron density from the DG eigenvectors (Eq. (10)) through the diagonal blocks of
+ * the density matrix (Eq. (11)): every ALB lives on its own element, so on E_k
+ * rho(r) = sum_{j,l} phi_{k,j}(r) P_kk[j, l] phi_{k,l}(r) with P_kk = C_k C_k^T, C_k the
+ * J_k rows of C that belong to element k.  alb_dev: the ALB values (dg_make_alb layout,
+ * DG_OFF_ALB: |E_k| x J_k column-major per element, Euclidean-normalised);
+ * c_dev: FP64 column-major (sum_k J_k) x n_e with leading dimension ldc >= sum_k J_k,
+ * element k's rows starting at its DG_OFF_EIG offset, one column per state with unit
+ * weight (fold occupations into the columns as sqrt(f_i)); p_dev: out, P_kk per
+ * element, J_k x J_k column-major (DG_OFF_JJ); rho_dev: out, rho on E_k's points
+ * (DG_OFF_ELEM), per grid point (sum over all points = trace C^T C; the physical
+ * density is rho / dV).  n_e = 0 gives zeros.  Needs no solve (pure function of its
+ * inputs and the element shapes); asynchronous on the caller's stream.  Errors:
+ * DG_ERR_ARG (NULL, n_e < 0, ldc too small), DG_ERR_HIP. */
+int32_t dg_density(dg_ctx *ctx, const double *alb_dev, const double *c_dev, int64_t ldc, int32_t n_e,
+                   double *p_dev, double *rho_dev);
+
 /* Band energy E = sum_i f_i psi_i^T H psi_i with Psi = p_m(H) Psi_0, p_m the
  * degree-m scaled Chebyshev filter of Algorithm 2 / Eq. (8) with bounds
  * (a, b, a0) per element (bounds_host: 3 host values per element, a0 < a < b;

@@ -28,7 +28,7 @@ import scipy.linalg
 
 from .planewave import apply_kinetic, hpsi, kinetic_symbol
 
-__all__ = ["teter_factor", "teter_apply", "lobpcg", "LobpcgResult", "orth_svd"]
+__all__ = ["teter_factor", "teter_apply", "lobpcg", "LobpcgResult", "orth_svd", "rayleigh_ritz"]
 
 
 def teter_factor(t: np.ndarray) -> np.ndarray:
@@ -56,6 +56,16 @@ def orth_svd(A: np.ndarray, scale: float, rel_drop: float = 1e-10) -> np.ndarray
         return A[:, :0]
     U, s, _ = np.linalg.svd(A, full_matrices=False)
     return U[:, s > rel_drop * scale]
+
+
+def rayleigh_ritz(el, X0: np.ndarray):
+    """Ritz pairs of H^{Q_k} on span(X0) (the start of Algorithm 1, step 1): an
+    orthonormal basis Q of span(X0) (Householder QR), the projected matrix Q^T H Q and
+    its eigendecomposition; returns (Ritz values ascending, Ritz vectors Q V)."""
+    Q, _ = np.linalg.qr(X0)
+    A = Q.T @ hpsi(el, Q)
+    theta, V = np.linalg.eigh(0.5 * (A + A.T))
+    return theta, Q @ V
 
 
 @dataclasses.dataclass

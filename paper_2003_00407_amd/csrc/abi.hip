@@ -592,6 +592,36 @@ int32_t dg_make_alb(dg_ctx* ctx, double* alb_dev, double* sval_dev) {
   })
 }
 
+int32_t dg_density(dg_ctx* ctx, const double* alb_dev, const double* c_dev, int64_t ldc, int32_t n_e,
+                   double* p_dev, double* rho_dev) {
+  if (!ctx) {
+    dg::set_error("ctx is NULL");
+    return DG_ERR_ARG;
+  }
+  DG_GUARD({
+    const int64_t rows = ctx->off[DG_OFF_EIG].back();
+    if (!alb_dev || !p_dev || !rho_dev || (n_e > 0 && !c_dev)) {
+      dg::set_error("alb_dev, p_dev, rho_dev (and c_dev when n_e > 0) must be non-NULL");
+      return DG_ERR_ARG;
+    }
+    if (n_e < 0 || (n_e > 0 && ldc < rows)) {
+      dg::set_error("n_e must be >= 0 and ldc >= " + std::to_string(rows) + " (the ALBs of all elements)");
+      return DG_ERR_ARG;
+    }
+    if (int st = ctx->fork()) return st;
+    int st = each_group(ctx, [&](int i) {
+      const int a = ctx->lo[i];
+      return dg::density(ctx->g[i], shift(alb_dev, ctx->off[DG_OFF_ALB][a], sizeof(double)),
+                         shift(c_dev, ctx->off[DG_OFF_EIG][a], sizeof(double)), n_e > 0 ? ldc : 1, n_e,
+                         shift(p_dev, ctx->off[DG_OFF_JJ][a], sizeof(double)),
+                         shift(rho_dev, ctx->off[DG_OFF_ELEM][a], sizeof(double)));
+    });
+    if (st < 0) return st;
+    if (int s2 = ctx->join()) return s2;
+    return st;
+  })
+}
+
 int32_t dg_band_energy(dg_ctx* ctx, int32_t prec, int32_t degree, const double* bounds_host,
                        int32_t n_vec, const void* psi0_dev, const double* f_dev, double* E_dev) {
   if (!ctx) {

@@ -337,6 +337,7 @@ int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, long long ldx,
 int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters);
 int get_vectors(Ctx& c, double* x);
 int make_alb(Ctx& c, double* alb, double* sval);
+int density(Ctx& c, const double* alb, const double* C, long long ldc, int n_e, double* P, double* rho);
 int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_vec, const void* psi0,
                 const double* f, double* E);
 int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv);

@@ -29,13 +29,13 @@ DG_OK, DG_WARN_NOT_CONVERGED = 0, 1
 DG_ERR_ARG, DG_ERR_SHAPE, DG_ERR_OOM, DG_ERR_HIP, DG_ERR_NUMERIC, DG_ERR_STATE = -1, -2, -3, -4, -5, -6
 DG_FP64, DG_MIXED, DG_FP32 = 0, 1, 2
 DG_LOBPCG, DG_CHFSI = 0, 1
-DG_OFF_X0, DG_OFF_VEC, DG_OFF_EIG, DG_OFF_ALB, DG_OFF_GRID, DG_OFF_KALL = range(6)
+DG_OFF_X0, DG_OFF_VEC, DG_OFF_EIG, DG_OFF_ALB, DG_OFF_GRID, DG_OFF_KALL, DG_OFF_ELEM, DG_OFF_JJ = range(8)
 
 EXPORTED = [
     "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
     "dg_query_offsets", "dg_apply_H", "dg_apply_H_noalloc", "dg_solve_elements", "dg_get_ritz", "dg_get_vectors", "dg_make_alb",
     "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing", "dg_timing_work",
-    "dg_query_hamiltonian", "dg_build_hamiltonian",
+    "dg_query_hamiltonian", "dg_build_hamiltonian", "dg_density",
 ]
 
 
@@ -95,6 +95,7 @@ _lib.dg_timing_work.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
 _lib.dg_query_hamiltonian.argtypes = [C.c_void_p, C.POINTER(MeshDesc), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
 _lib.dg_build_hamiltonian.argtypes = [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.c_void_p, C.c_size_t]
+_lib.dg_density.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]
 
 
 class DGError(RuntimeError):
@@ -372,6 +373,27 @@ class Elements:
                 nb = int(col[b])
                 out[(k, nb)] = Hh[off[b]:off[b + 1]].reshape(Js[nb], Js[k]).T
         return out
+
+    def density(self, alb, C_coef, n_e: int = -1, ldc: int = 0):
+        """(P diagonal blocks, rho) from the ALB values (make_alb) and the FP64 DG
+        coefficients C_coef: a column-major (sum J_k) x n_e device tensor given as
+        its transpose, i.e. a row-major (n_e, ldc) tensor; see dg_density."""
+        torch = self.torch
+        if n_e < 0:
+            n_e = int(C_coef.shape[0]) if C_coef is not None else 0
+        if C_coef is not None:
+            if C_coef.dtype != torch.float64 or not C_coef.is_cuda or C_coef.dim() != 2 or \
+                    (C_coef.shape[1] > 1 and C_coef.stride(1) != 1):
+                raise ValueError("C_coef must be a 2-D CUDA float64 tensor with unit column stride")
+            if ldc == 0:
+                # a single state's row stride is not meaningful (torch may report any value)
+                ldc = int(C_coef.shape[1]) if C_coef.shape[0] <= 1 else int(C_coef.stride(0))
+        P = self._dev(int(self.offsets(DG_OFF_JJ)[-1]), torch.float64)
+        rho = self._dev(int(self.offsets(DG_OFF_ELEM)[-1]), torch.float64)
+        cp = C.c_void_p(C_coef.data_ptr()) if C_coef is not None else None
+        _check(_lib.dg_density(self.ctx, C.c_void_p(alb.data_ptr()), cp, C.c_int64(ldc), C.c_int32(n_e),
+                               C.c_void_p(P.data_ptr()), C.c_void_p(rho.data_ptr())), "dg_density")
+        return P, rho
 
     TIMING_CLASSES = ("plane", "zcol", "nonlocal", "teter", "gram", "rotate", "rayleigh_ritz", "other")
 

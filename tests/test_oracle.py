@@ -381,3 +381,21 @@ def test_band_energy_grad_fd_v():
               - band_energy.band_energy(el, el.v_eff - h * d, psi0, f, m, a, b, a0)) / (2 * h)
         an = gv @ d
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0)
+
+
+def test_rayleigh_ritz_full_span_and_interlacing():
+    """On a tiny element: Ritz values of a full-rank start are the eigenvalues of the
+    dense Hamiltonian; for a smaller start they lie above the lowest eigenvalues
+    (Cauchy interlacing: theta_i >= lambda_i) and each Ritz pair's residual is
+    orthogonal to the span."""
+    el = tiny_element(n=(8, 8, 8), length=(6.0, 6.4, 7.2), n_states=6)
+    lam = np.linalg.eigvalsh(planewave.dense_H(el))
+    x0 = W.initial_block(el.npts, el.npts, 4).T
+    theta, X = lobpcg.rayleigh_ritz(el, x0)
+    assert np.max(np.abs(theta - lam)) < 1e-10 * np.max(np.abs(lam))
+    x0 = W.initial_block(el.npts, 9, 5).T
+    theta, X = lobpcg.rayleigh_ritz(el, x0)
+    assert np.all(theta >= lam[:9] - 1e-12)
+    R = planewave.hpsi(el, X) - X * theta
+    assert np.max(np.abs(X.T @ R)) < 1e-11 * np.max(np.abs(lam))
+    assert np.max(np.abs(X.T @ X - np.eye(9))) < 1e-13
