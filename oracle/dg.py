@@ -39,7 +39,8 @@ import scipy.fft
 
 from .planewave import n_workers
 
-__all__ = ["alb_coefficients", "spectral_gradient", "face_traces", "dg_hamiltonian", "dense_from_blocks"]
+__all__ = ["alb_coefficients", "spectral_gradient", "face_traces", "dg_hamiltonian", "dense_from_blocks",
+           "apply_blocks", "dg_chefsi"]
 
 
 def alb_coefficients(el, X: np.ndarray, J: int):
@@ -183,3 +184,25 @@ def dense_from_blocks(blocks, Js):
     for (kp, k), B in blocks.items():
         H[off[kp]:off[kp + 1], off[k]:off[k + 1]] += B
     return H
+
+
+def apply_blocks(blocks, Js, X: np.ndarray) -> np.ndarray:
+    """H^DG X one element row at a time (Eq. (8)): the rows of element k are
+    sum over the nonzero blocks (k, k') of H_{k,k'} X_{k'}, X_{k'} the rows of element
+    k' (element-major rows, J_k per element)."""
+    off = np.concatenate([[0], np.cumsum(Js)]).astype(np.int64)
+    Y = np.zeros((off[-1], X.shape[1]))
+    for (k, kp), B in blocks.items():
+        Y[off[k]:off[k + 1], :] += B @ X[off[kp]:off[kp + 1], :]
+    return Y
+
+
+def dg_chefsi(blocks, Js, x0: np.ndarray, n_want: int, degree: int = 16, tol: float = 1e-10,
+              max_iter: int = 200):
+    """Lowest eigenpairs of H^DG by Algorithm 2 (CheFSI) with the block-sparse product
+    of Eq. (8): the Chebyshev-filtered subspace iteration of ``oracle.chebyshev.chfsi``
+    (Lanczos upper bound, lower bound from the previous Ritz values, Cholesky
+    orthonormalisation, projected eigenproblem, rotation) applied to H^DG."""
+    from .chebyshev import chfsi
+    return chfsi(None, x0, n_want, degree=degree, tol=tol, max_iter=max_iter,
+                 apply_h=lambda V: apply_blocks(blocks, Js, V))
