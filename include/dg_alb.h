@@ -281,6 +281,42 @@ int32_t dg_query_hamiltonian(const dg_ctx *ctx, const dg_mesh_desc *mesh, int32_
 int32_t dg_build_hamiltonian(dg_ctx *ctx, const dg_mesh_desc *mesh, double *hdg_dev, void *work_dev,
                              size_t work_bytes);
 
+/* CheFSI on the DG Hamiltonian (Algorithm 2; H^DG X by the block-row product of
+ * Eq. (8)). */
+typedef struct {
+  int32_t n_want;        /* wanted lowest eigenpairs N_e (the residual test)          */
+  int32_t n_vec;         /* block width N_e + guards, <= 88 and <= N_b / 2            */
+  int32_t degree;        /* Chebyshev filter degree m (1..64; the paper uses 10-40)   */
+  int32_t max_iter;      /* filter passes (each: filter, Cholesky-QR, projected eig)   */
+  double tol;            /* max ||H x_i - theta_i x_i|| over the wanted pairs          */
+  int32_t lanczos_steps; /* steps of the Lanczos run for b_up (0: 10)                  */
+  int32_t reserved;      /* 0                                                          */
+  int64_t seed;          /* Lanczos start vector (counter-based Gaussian draw)         */
+} dg_chefsi_params;
+
+/* Device workspace bytes of dg_chefsi for a block-sparse H^DG with n_blocks blocks
+ * over this context's elements (N_b = sum_k J_k rows) and n_vec columns.  CPU only.
+ * Errors: DG_ERR_ARG. */
+int32_t dg_query_chefsi(const dg_ctx *ctx, int32_t n_blocks, int32_t n_vec, size_t *work_bytes);
+
+/* Lowest eigenpairs of H^DG by CheFSI (Algorithm 2): b_up from a Lanczos run, b_low
+ * and the lowest-eigenvalue estimate from the previous Ritz values (the first from a
+ * Rayleigh-Ritz step on the start block), then per pass the degree-m filter, Cholesky
+ * orthonormalisation, projected eigenproblem and rotation, until the n_want residuals
+ * are below tol.  The matrix is given as dg_build_hamiltonian writes it: hdg_dev on
+ * the device with the host layout row_ptr (n_elem + 1), col_idx (n_blocks), block_off
+ * (n_blocks + 1), rows of element k being its J_k ALBs (DG_OFF_EIG offsets).
+ * x_dev: in: the start block, column-major N_b x n_vec (ld N_b), full rank; out: the
+ * Ritz vectors, ascending.  eig_dev, resid_dev: n_vec Ritz values and residual norms.
+ * work_dev: dg_query_chefsi bytes, 256-byte aligned.  Runs on the caller's stream and
+ * returns after it.  Returns DG_WARN_NOT_CONVERGED when tol was missed after max_iter.
+ * Errors: DG_ERR_ARG (NULL, layout that does not match the elements' J_k, parameters
+ * out of range), DG_ERR_SHAPE (n_vec above 88 or N_b / 2), DG_ERR_OOM (work too small),
+ * DG_ERR_NUMERIC (non-finite residual, rank-deficient start block), DG_ERR_HIP. */
+int32_t dg_chefsi(dg_ctx *ctx, const dg_chefsi_params *params, int32_t n_blocks, const int64_t *row_ptr,
+                  const int32_t *col_idx, const int64_t *block_off, const double *hdg_dev, double *x_dev,
+                  double *eig_dev, double *resid_dev, void *work_dev, size_t work_bytes, int32_t *iters_host);
+
 /* Electron density from the DG eigenvectors (Eq. (10)) through the diagonal blocks of
  * the density matrix (Eq. (11)): every ALB lives on its own element, so on E_k
  * rho(r) = sum_{j,l} phi_{k,j}(r) P_kk[j, l] phi_{k,l}(r) with P_kk = C_k C_k^T, C_k the

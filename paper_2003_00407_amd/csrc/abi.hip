@@ -592,6 +592,49 @@ int32_t dg_make_alb(dg_ctx* ctx, double* alb_dev, double* sval_dev) {
   })
 }
 
+namespace {
+std::vector<int> batch_J(const dg_ctx* ctx) {
+  std::vector<int> Js;
+  for (const Ctx& c : ctx->g) Js.insert(Js.end(), c.J.begin(), c.J.end());
+  return Js;
+}
+}  // namespace
+
+int32_t dg_query_chefsi(const dg_ctx* ctx, int32_t n_blocks, int32_t n_vec, size_t* work_bytes) {
+  if (!ctx || !work_bytes || n_blocks < 0 || n_vec < 1) {
+    dg::set_error("ctx and work_bytes must be non-NULL, n_blocks >= 0, n_vec >= 1");
+    return DG_ERR_ARG;
+  }
+  DG_GUARD({
+    const std::vector<int> Js = batch_J(ctx);
+    long long nb = 0;
+    for (int j : Js) nb += j;
+    *work_bytes = dg::chefsi_work_bytes((int)Js.size(), (int)nb, n_vec, n_blocks);
+    return DG_OK;
+  })
+}
+
+int32_t dg_chefsi(dg_ctx* ctx, const dg_chefsi_params* params, int32_t n_blocks, const int64_t* row_ptr,
+                  const int32_t* col_idx, const int64_t* block_off, const double* hdg_dev, double* x_dev,
+                  double* eig_dev, double* resid_dev, void* work_dev, size_t work_bytes, int32_t* iters_host) {
+  if (!ctx || !params || !row_ptr || !block_off || (n_blocks > 0 && !col_idx) || !hdg_dev || !x_dev || !eig_dev ||
+      !resid_dev || !work_dev || n_blocks < 0) {
+    dg::set_error("NULL argument or n_blocks < 0");
+    return DG_ERR_ARG;
+  }
+  if (((uintptr_t)work_dev & 255) != 0) {
+    dg::set_error("work_dev must be 256-byte aligned");
+    return DG_ERR_ARG;
+  }
+  DG_GUARD({
+    int it = 0;
+    const int st = dg::chefsi(ctx->user, batch_J(ctx), *params, n_blocks, row_ptr, col_idx, block_off, hdg_dev,
+                              x_dev, eig_dev, resid_dev, work_dev, work_bytes, &it);
+    if (iters_host) *iters_host = it;
+    return st;
+  })
+}
+
 int32_t dg_density(dg_ctx* ctx, const double* alb_dev, const double* c_dev, int64_t ldc, int32_t n_e,
                    double* p_dev, double* rho_dev) {
   if (!ctx) {

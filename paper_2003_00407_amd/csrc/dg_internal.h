@@ -162,6 +162,20 @@ struct PendingTime {
   hipEvent_t a, b;
 };
 
+// H^DG as a block-sparse operator for the CheFSI on the global problem (device tables):
+// element row k holds blocks row_ptr[k]..row_ptr[k+1] (column element col_idx[b],
+// J_k x J_col column-major at H + boff[b]); roff: first row of each element
+struct DgOp {
+  int M = 0;
+  bool active = false;      // the context's "H" is this operator (one pseudo-element)
+  const double* H = nullptr;
+  const long long* row_ptr = nullptr;
+  const int* col_idx = nullptr;
+  const long long* boff = nullptr;
+  const long long* roff = nullptr;
+  const int* J = nullptr;
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   int n_elem = 0;
@@ -235,6 +249,7 @@ struct Ctx {
   bool orth_w = false;                         // W <- W - X (X^T W) before the projected problem
                                                // (DG_ORTH_W=1); by default the overlap S^T S carries it                        // DG_TUNE=0 keeps the default splits
   int nl_pending_np = 0, nl_pending_kk = 0;
+  DgOp dg_op;                      // set: H*psi is the block-sparse H^DG product
   int kmax = 0;                    // max K over elements
   int log_level = 0;               // DG_LOG environment variable
   double rr_pivot_tol = 1e-13;     // overlap-Cholesky breakdown threshold (FP64 data)
@@ -338,6 +353,11 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
 int get_vectors(Ctx& c, double* x);
 int make_alb(Ctx& c, double* alb, double* sval);
 int density(Ctx& c, const double* alb, const double* C, long long ldc, int n_e, double* P, double* rho);
+int launch_dg_bsr(Ctx& c, int in_blk, int out_blk, int ncols, const int* active);
+size_t chefsi_work_bytes(int M, int Nb, int K, int n_blocks);
+int chefsi(hipStream_t stream, const std::vector<int>& Js, const dg_chefsi_params& p, int n_blocks,
+           const int64_t* row_ptr, const int32_t* col_idx, const int64_t* block_off, const double* hdg,
+           double* x, double* eig, double* resid, void* work, size_t work_bytes, int* iters_out);
 int band_energy(Ctx& c, int prec, int degree, const double* bounds_host, int n_vec, const void* psi0,
                 const double* f, double* E);
 int band_energy_backward(Ctx& c, const double* dE_host, void* dpsi0, void* dv);

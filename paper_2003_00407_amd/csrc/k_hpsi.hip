@@ -686,6 +686,7 @@ static int hpsi_typed(Ctx& c, int elem, int ncols, int in_blk, int out_blk, cons
 }
 
 int launch_hpsi(Ctx& c, int elem, int ncols, int prec, int in_blk, int out_blk, const int* active) {
+  if (c.dg_op.active) return launch_dg_bsr(c, in_blk, out_blk, ncols, active);
   return prec == DG_FP64 ? hpsi_typed<double>(c, elem, ncols, in_blk, out_blk, active)
                          : hpsi_typed<float>(c, elem, ncols, in_blk, out_blk, active);
 }

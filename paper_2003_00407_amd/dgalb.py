@@ -35,7 +35,7 @@ EXPORTED = [
     "dg_status_string", "dg_last_error", "dg_query_workspace", "dg_create_elements", "dg_destroy",
     "dg_query_offsets", "dg_apply_H", "dg_apply_H_noalloc", "dg_solve_elements", "dg_get_ritz", "dg_get_vectors", "dg_make_alb",
     "dg_band_energy", "dg_band_energy_backward", "dg_set_potential", "dg_timing", "dg_timing_work",
-    "dg_query_hamiltonian", "dg_build_hamiltonian", "dg_density",
+    "dg_query_hamiltonian", "dg_build_hamiltonian", "dg_density", "dg_query_chefsi", "dg_chefsi",
 ]
 
 
@@ -58,6 +58,11 @@ class SolveParams(C.Structure):
                 ("tol_mixed", C.c_double), ("max_iter", C.c_int32), ("cheb_degree", C.c_int32),
                 ("x0_dev", C.c_void_p), ("graph_iters", C.c_int32), ("seed", C.c_int64),
                 ("warm_start", C.c_int32)]
+
+
+class ChefsiParams(C.Structure):
+    _fields_ = [("n_want", C.c_int32), ("n_vec", C.c_int32), ("degree", C.c_int32), ("max_iter", C.c_int32),
+                ("tol", C.c_double), ("lanczos_steps", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_int64)]
 
 
 class MeshDesc(C.Structure):
@@ -95,6 +100,10 @@ _lib.dg_timing_work.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
 _lib.dg_query_hamiltonian.argtypes = [C.c_void_p, C.POINTER(MeshDesc), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
 _lib.dg_build_hamiltonian.argtypes = [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.c_void_p, C.c_size_t]
+_lib.dg_query_chefsi.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+_lib.dg_chefsi.argtypes = [C.c_void_p, C.POINTER(ChefsiParams), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                           C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_size_t, C.POINTER(C.c_int32)]
 _lib.dg_density.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]
 
 
@@ -373,6 +382,34 @@ class Elements:
                 nb = int(col[b])
                 out[(k, nb)] = Hh[off[b]:off[b + 1]].reshape(Js[nb], Js[k]).T
         return out
+
+    def chefsi(self, H, layout, x0, n_want: int, degree: int = 16, tol: float = 1e-9, max_iter: int = 100,
+               lanczos_steps: int = 10, seed: int = 0):
+        """Lowest eigenpairs of H^DG (build_hamiltonian's H and layout) by CheFSI from the
+        start block x0 (a (n_vec, N_b) row-major CUDA float64 tensor = column-major
+        N_b x n_vec); returns (X like x0, Ritz values, residuals, iterations, status)."""
+        torch = self.torch
+        row_ptr, col, off = layout
+        n_vec, nb = int(x0.shape[0]), int(x0.shape[1])
+        if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
+            raise ValueError("x0 must be a contiguous CUDA float64 tensor")
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        wb = C.c_size_t(0)
+        _check(_lib.dg_query_chefsi(self.ctx, len(col), n_vec, C.byref(wb)), "dg_query_chefsi")
+        work = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
+        wp = (work.data_ptr() + 255) // 256 * 256
+        X = x0.clone()
+        eig = self._dev(n_vec, torch.float64)
+        res = self._dev(n_vec, torch.float64)
+        it = C.c_int32(0)
+        p = ChefsiParams(n_want, n_vec, degree, max_iter, tol, lanczos_steps, 0, int(seed))
+        st = _check(_lib.dg_chefsi(self.ctx, C.byref(p), len(col), _ptr(row_ptr, C.c_int64), _ptr(col, C.c_int32),
+                                   _ptr(off, C.c_int64), C.c_void_p(H.data_ptr()), C.c_void_p(X.data_ptr()),
+                                   C.c_void_p(eig.data_ptr()), C.c_void_p(res.data_ptr()), C.c_void_p(wp),
+                                   C.c_size_t(wb.value), C.byref(it)), "dg_chefsi")
+        return X, eig, res, int(it.value), st
 
     def density(self, alb, C_coef, n_e: int = -1, ldc: int = 0):
         """(P diagonal blocks, rho) from the ALB values (make_alb) and the FP64 DG

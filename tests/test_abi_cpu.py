@@ -127,6 +127,33 @@ def test_solve_params_layout_matches_header():
     assert ctypes.sizeof(P) == 64
 
 
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every ctypes mirror against offsetof/sizeof as gcc lays out the header's structs."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    d = _lib()
+    mirrors = {"dg_solve_params": d.SolveParams, "dg_chefsi_params": d.ChefsiParams, "dg_mesh_desc": d.MeshDesc}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dg_alb.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, field, value = line.split()
+        py = mirrors[cname]
+        got = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert got == int(value), f"{cname}.{field}: ctypes {got}, C {value}"
+
+
 def test_null_context_calls_fail_cleanly():
     d = _lib()
     lib = d._lib
@@ -135,6 +162,9 @@ def test_null_context_calls_fail_cleanly():
     assert lib.dg_solve_elements(None, None, None, None, None) == d.DG_ERR_ARG
     assert lib.dg_make_alb(None, None, None) == d.DG_ERR_ARG
     assert lib.dg_get_vectors(None, None) == d.DG_ERR_ARG
+    assert lib.dg_density(None, None, None, 0, 0, None, None) == d.DG_ERR_ARG
+    assert lib.dg_chefsi(None, None, 0, None, None, None, None, None, None, None, None, 0, None) == d.DG_ERR_ARG
+    assert lib.dg_query_chefsi(None, 0, 1, None) == d.DG_ERR_ARG
     lib.dg_destroy(None)
 
 

@@ -49,6 +49,7 @@ def _run(els, mesh, X0):
     hm = D.HostMesh((mesh.n_mesh, mesh.n_mesh), ALPHA, [mesh.elem_projectors(k) for k in range(len(els))])
     H, layout = E.build_hamiltonian(hm)
     c.blocks = E.hamiltonian_blocks(H, layout)
+    c.H, c.layout = H, layout
     c.E, c.alb, c.D = E, alb, D
     # oracle
     c.X = [olob.rayleigh_ritz(el, X0[k])[1] for k, el in enumerate(els)]
@@ -245,3 +246,110 @@ def test_density_edge_cases(small_slab):
     P1, rho1 = c.E.density(c.alb, Ct, n_e=5, ldc=n_rows + 7)
     rho2, _ = _gpu_density(c, C)
     assert np.array_equal(rho1.cpu().numpy(), np.concatenate(rho2))
+
+
+# ---------------------------------------------------------------------------
+# CheFSI on H^DG (Algorithm 2)
+# ---------------------------------------------------------------------------
+def _pack_blocks(c, blocks):
+    """A block dict in the device layout of build_hamiltonian (absent blocks zero)."""
+    torch = need_torch_cuda()
+    row_ptr, col, off = c.layout
+    flat = np.zeros(int(off[-1]))
+    for k in range(len(c.els)):
+        for b in range(int(row_ptr[k]), int(row_ptr[k + 1])):
+            B = blocks.get((k, int(col[b])))
+            if B is not None:
+                flat[off[b]:off[b + 1]] = B.T.ravel()      # column-major J_k x J_col
+    return torch.tensor(flat, dtype=torch.float64, device="cuda")
+
+
+def _chefsi_case(c, n_want, n_vec, degree, tol, seed=31, max_iter=200):
+    """GPU CheFSI on the oracle's H^DG against the dense eigendecomposition of the same
+    matrix and against the oracle's CheFSI (Algorithm 2) from the same start."""
+    torch = need_torch_cuda()
+    Ho = odg.dense_from_blocks(c.ref, c.Js)
+    Nb = Ho.shape[0]
+    x0 = W.initial_block(Nb, n_vec, seed)                 # (n_vec, N_b): column-major N_b x n_vec
+    X, eig, res, it, st = c.E.chefsi(_pack_blocks(c, c.ref), c.layout,
+                                     torch.tensor(x0, dtype=torch.float64, device="cuda"), n_want,
+                                     degree=degree, tol=tol, max_iter=max_iter)
+    lam, V = np.linalg.eigh(Ho)
+    Xg = X.cpu().numpy().T
+    th = eig.cpu().numpy()
+    r = res.cpu().numpy()
+    orc = odg.dg_chefsi(c.ref, c.Js, x0.T, n_want, degree=degree, tol=tol, max_iter=max_iter)
+    gap = lam[n_want] - lam[n_want - 1]
+    Pd = Xg[:, :n_want] @ Xg[:, :n_want].T - V[:, :n_want] @ V[:, :n_want].T
+    true_res = np.linalg.norm(Ho @ Xg[:, :n_want] - Xg[:, :n_want] * th[:n_want], axis=0)
+    print(f"[chefsi] N_b {Nb} n_want {n_want} n_vec {n_vec} m {degree}: status {st}, {it} passes (oracle "
+          f"{orc.iters}); max |theta - lambda| {np.max(np.abs(th[:n_want] - lam[:n_want])):.1e}, reported "
+          f"residual {r[:n_want].max():.1e}, recomputed {true_res.max():.1e}, subspace {np.linalg.norm(Pd, 2):.1e} "
+          f"(gap {gap:.3f})", flush=True)
+    return st, it, th, r, true_res, lam, Pd, gap, orc
+
+
+@pytest.mark.parametrize("case,n_want,n_vec,degree", [("small_slab", 20, 24, 12), ("c2_slab", 60, 72, 16)])
+def test_chefsi_on_dg_hamiltonian_vs_dense_and_oracle(case, n_want, n_vec, degree, request):
+    """Ritz values within the residual bound |theta_i - lambda_i| <= ||r_i||, the wanted
+    subspace within ||r|| / gap (Davis-Kahan), residuals recomputed on the host agree
+    with the reported ones, and the oracle's CheFSI from the same start converges to the
+    same pairs."""
+    c = request.getfixturevalue(case)
+    tol = 1e-9
+    st, it, th, r, true_res, lam, Pd, gap, orc = _chefsi_case(c, n_want, n_vec, degree, tol)
+    assert st == 0 and orc.converged
+    assert r[:n_want].max() <= tol and true_res.max() <= 2 * tol
+    assert np.max(np.abs(th[:n_want] - lam[:n_want])) <= 2 * tol
+    assert np.linalg.norm(Pd, 2) <= 10 * tol * np.sqrt(n_want) / gap
+    assert np.max(np.abs(th[:n_want] - orc.eigvals[:n_want])) <= 4 * tol
+
+
+def test_chefsi_edge_cases(small_slab):
+    """One pass cannot reach 1e-12 (a warning with finite output); a start block with a
+    repeated column is rank deficient (a numeric error); a block wider than N_b / 2 is a
+    shape error; a layout whose block sizes do not match the elements is an argument
+    error."""
+    torch = need_torch_cuda()
+    c = small_slab
+    D = c.D
+    Ho = odg.dense_from_blocks(c.ref, c.Js)
+    Nb = Ho.shape[0]
+    Hdev = _pack_blocks(c, c.ref)
+    x0 = torch.tensor(W.initial_block(Nb, 24, 5), dtype=torch.float64, device="cuda")
+    X, eig, res, it, st = c.E.chefsi(Hdev, c.layout, x0, 20, degree=8, tol=1e-12, max_iter=1)
+    assert st == D.DG_WARN_NOT_CONVERGED and it == 1
+    assert np.all(np.isfinite(eig.cpu().numpy())) and np.all(np.isfinite(X.cpu().numpy()))
+    xd = x0.clone()
+    xd[3] = xd[2]
+    with pytest.raises(D.DGError) as e:
+        c.E.chefsi(Hdev, c.layout, xd, 20, degree=8, tol=1e-9)
+    assert e.value.status == D.DG_ERR_NUMERIC
+    with pytest.raises(D.DGError) as e:
+        c.E.chefsi(Hdev, c.layout, torch.zeros((37, Nb), dtype=torch.float64, device="cuda"), 20)
+    assert e.value.status == D.DG_ERR_SHAPE
+    row_ptr, col, off = c.layout
+    bad = (row_ptr, col, off.copy())
+    bad[2][1:] += 1
+    with pytest.raises(D.DGError) as e:
+        c.E.chefsi(Hdev, bad, x0, 20)
+    assert e.value.status == D.DG_ERR_ARG
+
+
+def test_chefsi_on_the_gpu_built_hamiltonian(c2_slab):
+    """The pipeline as it runs: the GPU's H^DG into the GPU's CheFSI.  Its Ritz values
+    match the oracle H^DG's eigenvalues to the Hamiltonians' own difference (the
+    basis rotation leaves the spectrum unchanged)."""
+    torch = need_torch_cuda()
+    c = c2_slab
+    Ho = odg.dense_from_blocks(c.ref, c.Js)
+    lam = np.linalg.eigvalsh(Ho)
+    Hg = odg.dense_from_blocks(c.blocks, c.Js)
+    dev = np.max(np.abs(np.linalg.eigvalsh(0.5 * (Hg + Hg.T)) - lam))
+    x0 = torch.tensor(W.initial_block(Ho.shape[0], 72, 8), dtype=torch.float64, device="cuda")
+    X, eig, res, it, st = c.E.chefsi(c.H, c.layout, x0, 60, degree=16, tol=1e-9)
+    th = eig.cpu().numpy()[:60]
+    print(f"[chefsi] GPU-built H^DG: {it} passes, max |theta - lambda_oracle| {np.max(np.abs(th - lam[:60])):.1e} "
+          f"(H difference {dev:.1e})", flush=True)
+    assert st == 0
+    assert np.max(np.abs(th - lam[:60])) <= 2e-9 + 10 * dev
