@@ -82,7 +82,7 @@ struct GramArgs {
 };
 
 constexpr int GP_THREADS = 512;
-constexpr int GP_R = 16;        // grid rows staged per step
+constexpr int GP_R = 32;        // grid rows staged per step
 constexpr int GP_MAXCOL = 384;  // staged columns per workgroup (tiles are chosen to fit)
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -183,6 +183,26 @@ __device__ __forceinline__ GramItem gram_item(const GramArgs& A) {
   return it;
 }
 
+// FP64 staging: column-major panels, GP_RP doubles per staged column (32 rows + 2 pad;
+// about 105 KB for 384 columns, one workgroup per CU).  Lane l reads rows 8 (l / 16) ..
+// 8 (l / 16) + 7 of column (l % 16) of a 16-column fragment as four 16-byte loads;
+// with a column pitch of 272 bytes any 8 (or 16) consecutive lanes of such a load fall
+// on distinct banks.  MFMA k-step j takes row 8 (l / 16) + j from every lane group: the
+// eight k-steps cover the 32 rows of the panel, the same assignment for both operands
+// (a Gram sums over rows in any order).
+constexpr int GP_RP = GP_R + 2;
+constexpr int GP_LDS_LIMIT = 120000;
+
+// Block b' of a wave's contiguous run: in pair mode the two products of one (p, q)
+// are adjacent (they share the A operand, S's column block p); blocks follow the
+// tile's row-major order, so runs share p as well.
+__device__ __forceinline__ void gram_run_block(const GramTile& g, int bprime, int pair, int offB, int offC,
+                                               int& acol, int& bcol, int& pos) {
+  const int lb = pair ? (bprime >> 1) : bprime;
+  const int second = pair ? (bprime & 1) : 0;
+  gram_tile_block(g, lb + second * g.nloc, offB, offC, acol, bcol, pos);
+}
+
 // PF: staged values per thread and step (32 columns per pass of the workgroup)
 template <typename T, int MAXB, int PF>
 __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
@@ -207,10 +227,9 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
   // LDS column of the B operand's first staged column, per product
   const int offB = (A.same && g.diag) ? 0 : g.ncA;
   const int offC = g.diag ? 0 : g.ncA + g.ncB;
-  const int pitch = nc + 1;
   extern __shared__ double gsm[];
-  double* sm = gsm;                                       // [GP_R][pitch]
-  const T** cp = reinterpret_cast<const T**>(gsm + GP_R * pitch);   // [nc]
+  double* sm = gsm;                                       // [nc][GP_RP]
+  const T** cp = reinterpret_cast<const T**>(gsm + (size_t)nc * GP_RP);   // [nc]
   for (int c = threadIdx.x; c < nc; c += GP_THREADS) {
     const T* ptr = nullptr;
     if (c < g.ncA) {
@@ -229,33 +248,35 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
     }
     cp[c] = ptr;
   }
-  // the wave index is uniform: the block bookkeeping below stays in scalar registers
+  // the wave index is uniform: the block bookkeeping below stays in scalar registers.
+  // Wave w owns the contiguous run [w cs, (w + 1) cs) of the tile's blocks; bp, bq: LDS
+  // columns of the A and B operands, bo: output position (row block, column block)
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // this wave's output blocks: w + 8 t of the tile's list (blocks nloc .. 2 nloc - 1
-  // are those of S^T S in pair mode); bp, bq: LDS columns of the A and B operands,
-  // bo: output position (row block, column block)
+  const int cs = (nblk_all + 7) >> 3;
   int bp[MAXB], bq[MAXB], bo[MAXB];
   bool bv[MAXB];
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) {
-    const int b = w + 8 * t;
-    bv[t] = b < nblk_all;
+    const int b = w * cs + t;
+    bv[t] = t < cs && b < nblk_all;
     bp[t] = bq[t] = bo[t] = 0;
-    if (bv[t]) gram_tile_block(g, b, offB, offC, bp[t], bq[t], bo[t]);
+    if (bv[t]) gram_run_block(g, b, A.pair, offB, offC, bp[t], bq[t], bo[t]);
   }
   const int l16 = lane & 15;
+  const int lrow = (lane >> 4) * (GP_R / 4);
   d4v acc[MAXB];
 #pragma unroll
   for (int t = 0; t < MAXB; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
   __syncthreads();
-  // staging map: thread -> grid row (tid % 16) of columns tid / 16 + 32 u
-  const int srow = threadIdx.x & (GP_R - 1), scol = threadIdx.x >> 4;
+  // staging map: thread -> grid row (tid % 32) of columns tid / 32 + 16 u
+  constexpr int kCPP = GP_THREADS / GP_R;   // columns per pass of the workgroup
+  const int srow = threadIdx.x & (GP_R - 1), scol = threadIdx.x / GP_R;
   double pre[PF];
   auto load = [&](int rbase) {
     const int rr = rbase + srow;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int c = scol + 32 * u;
+      const int c = scol + kCPP * u;
       double v = 0.0;
       if (c < nc) {
         const T* ptr = cp[c];
@@ -264,22 +285,37 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
       pre[u] = v;
     }
   };
+  constexpr int KF = GP_R / 4;   // k-steps per panel = values per lane and fragment
+  auto frag = [&](int col, double (&f)[KF]) {
+    const double2* q = reinterpret_cast<const double2*>(sm + (size_t)(col + l16) * GP_RP + lrow);
+#pragma unroll
+    for (int m = 0; m < KF / 2; ++m) {
+      const double2 x = q[m];
+      f[2 * m] = x.x;
+      f[2 * m + 1] = x.y;
+    }
+  };
   if (r0 < r1) load(r0);
   for (int r = r0; r < r1; r += GP_R) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int c = scol + 32 * u;
-      if (c < nc) sm[srow * pitch + c] = pre[u];
+      const int c = scol + kCPP * u;
+      if (c < nc) sm[(size_t)c * GP_RP + srow] = pre[u];
     }
     __syncthreads();
     if (r + GP_R < r1) load(r + GP_R);
+    double fa[KF];
 #pragma unroll
-    for (int ks = 0; ks < GP_R / 4; ++ks) {
-      const int rowoff = (ks * 4 + (lane >> 4)) * pitch;
+    for (int j = 0; j < KF; ++j) fa[j] = 0.0;
 #pragma unroll
-      for (int t = 0; t < MAXB; ++t)
-        if (bv[t]) acc[t] = mfma16x16x4(sm[rowoff + l16 + bp[t]], sm[rowoff + l16 + bq[t]], acc[t]);
+    for (int t = 0; t < MAXB; ++t) {
+      if (!bv[t]) continue;
+      if (t == 0 || bp[t] != bp[t - 1]) frag(bp[t], fa);   // uniform branch: bp is wave-uniform
+      double fb[KF];
+      frag(bq[t], fb);
+#pragma unroll
+      for (int j = 0; j < KF; ++j) acc[t] = mfma16x16x4(fa[j], fb[j], acc[t]);
     }
   }
   double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
@@ -1189,8 +1225,19 @@ constexpr int RT_NCT = RT_MAXC / 16;
 // results are 16 consecutive grid rows of one column (128-byte stores).
 // With two outputs whose C row ranges nest (range 1 is a suffix of range 0),
 // the suffix is accumulated first, stored as output 1, then completed.
+// C rows of a chunk are staged transposed: for each output column n, its RT_CC
+// coefficients contiguous (pitch RT_CP doubles).  Lane l takes the 8 coefficients
+// k = 8 (l / 16) .. 8 (l / 16) + 7 of column (l % 16) of a 16-column tile with four
+// 16-byte LDS loads (pitch 272 bytes: 8 or 16 consecutive lanes on distinct banks);
+// MFMA k-step ks uses k = 8 (l / 16) + ks, and the S operand follows the same
+// assignment.  The two 16-row tiles of a wave interleave (lane row 2 (l % 16) + u), so
+// a lane's two S values of a column, and its two outputs, are adjacent in memory and
+// move as one 16-byte access.
+constexpr int RT_CP = RT_CC + 2;
+
 template <typename T, int NCT>
 __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs A) {
+  static_assert(sizeof(T) == 8 && RT_RT == 2, "FP64 rotation with two interleaved row tiles per lane");
   const int e = blockIdx.y;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) return;
@@ -1205,12 +1252,12 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
     c0[o] = A.c_blockrows > 0 ? A.c0[o] * kS : A.c0[o];
     c1[o] = A.c_blockrows > 0 ? A.c1[o] * kS : A.c1[o];
   }
-  __shared__ double sc[RT_CC][RT_MAXC + 1];
+  __shared__ double sc[NCT * 16][RT_CP];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int kl = lane >> 4;
-  int rrow[RT_RT];
-#pragma unroll
-  for (int u = 0; u < RT_RT; ++u) rrow[u] = r0 + (w * RT_RT + u) * 16 + (lane & 15);
+  // rows of this lane: rr0, rr0 + 1 (u = 0, 1)
+  const int rr0 = r0 + w * RT_RT * 16 + 2 * (lane & 15);
+  const bool in0 = rr0 < nrows, in1 = rr0 + 1 < nrows;
   const int nct = (ncol + 15) / 16;
   const double* Cm = E.small + soff(A.c_off, E);
   d4v acc[RT_RT][NCT];
@@ -1234,10 +1281,18 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
     auto load_s = [&](int cb, double (&dst)[RT_CC / 4][RT_RT]) {
 #pragma unroll
       for (int ks = 0; ks < RT_CC / 4; ++ks) {
-        const int c = cb + ks * 4 + kl;
+        const int c = cb + kl * (RT_CC / 4) + ks;
         const T* col = c < hi ? vcol<T>(E, A.S, c, kS) : nullptr;
-#pragma unroll
-        for (int u = 0; u < RT_RT; ++u) dst[ks][u] = (col && rrow[u] < nrows) ? double(col[rrow[u]]) : 0.0;
+        double x0 = 0.0, x1 = 0.0;
+        if (col && in1) {
+          const double2 v = *reinterpret_cast<const double2*>(col + rr0);
+          x0 = v.x;
+          x1 = v.y;
+        } else if (col && in0) {
+          x0 = double(col[rr0]);
+        }
+        dst[ks][0] = x0;
+        dst[ks][1] = x1;
       }
     };
     // with six column tiles (two waves per SIMD, registers to spare) the C rows of the
@@ -1265,13 +1320,13 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
           const int idx = threadIdx.x + u * RT_THREADS;
-          if (idx < RT_CC * NCT * 16) sc[idx / (NCT * 16)][idx % (NCT * 16)] = cn[u];
+          if (idx < RT_CC * NCT * 16) sc[idx % (NCT * 16)][idx / (NCT * 16)] = cn[u];
         }
       } else {
         for (int idx = threadIdx.x; idx < RT_CC * NCT * 16; idx += RT_THREADS) {
           const int cc = idx / (NCT * 16), j = idx % (NCT * 16);
           const int c = cb + cc;
-          sc[cc][j] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+          sc[j][cc] = (c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
         }
       }
 #pragma unroll
@@ -1284,19 +1339,26 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
         if constexpr (kPrefC) load_c(cb + RT_CC);
       }
 #pragma unroll
-      for (int ks = 0; ks < RT_CC / 4; ++ks) {
+      for (int t = 0; t < NCT; ++t) {
+        if (t >= nct) continue;
+        const double2* q = reinterpret_cast<const double2*>(&sc[t * 16 + (lane & 15)][kl * (RT_CC / 4)]);
+        double cf[RT_CC / 4];
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) {
-          if (t >= nct) continue;
-          const double cv = sc[ks * 4 + kl][t * 16 + (lane & 15)];
-#pragma unroll
-          for (int u = 0; u < RT_RT; ++u) acc[u][t] = mfma16x16x4(cv, av[ks][u], acc[u][t]);
+        for (int m = 0; m < RT_CC / 8; ++m) {
+          const double2 v = q[m];
+          cf[2 * m] = v.x;
+          cf[2 * m + 1] = v.y;
         }
+#pragma unroll
+        for (int ks = 0; ks < RT_CC / 4; ++ks)
+#pragma unroll
+          for (int u = 0; u < RT_RT; ++u) acc[u][t] = mfma16x16x4(cf[ks], av[ks][u], acc[u][t]);
       }
     }
-    // store the output this segment completes: lane holds out[row rrow[u]][col 16 t + kl + 4 q]
+    // store the output this segment completes: lane holds out[rows rr0, rr0 + 1][col 16 t + kl + 4 q]
     const int o = (A.nout > 1 && sg == 0) ? 1 : 0;
     T* out = reinterpret_cast<T*>(E.blk[A.out_blk[o]]);
+    const double beta = A.beta[o];
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
       if (t >= nct) continue;
@@ -1304,12 +1366,18 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
       for (int q = 0; q < 4; ++q) {
         const int j = t * 16 + kl + 4 * q;
         if (j >= ncol) continue;
-#pragma unroll
-        for (int u = 0; u < RT_RT; ++u) {
-          if (rrow[u] >= nrows) continue;
-          T* p = out + (size_t)j * E.ld + rrow[u];
-          const double prev = A.beta[o] != 0.0 ? A.beta[o] * double(*p) : 0.0;
-          *p = T(prev + A.alpha * acc[u][t][q]);
+        T* p = out + (size_t)j * E.ld + rr0;
+        if (in1) {
+          double2 v = {A.alpha * acc[0][t][q], A.alpha * acc[1][t][q]};
+          if (beta != 0.0) {
+            const double2 prev = *reinterpret_cast<const double2*>(p);
+            v.x += beta * prev.x;
+            v.y += beta * prev.y;
+          }
+          *reinterpret_cast<double2*>(p) = v;
+        } else if (in0) {
+          const double prev = beta != 0.0 ? beta * double(*p) : 0.0;
+          *p = T(prev + A.alpha * acc[0][t][q]);
         }
       }
     }
@@ -1779,9 +1847,9 @@ static bool set_lds_limit(const void* fn, int bytes) {
 // in registers.
 template <int MB>
 static void gram_attrs() {
-  set_lds_limit((const void*)k_gram<double, MB, 4>, 64000);
-  set_lds_limit((const void*)k_gram<double, MB, 8>, 64000);
-  set_lds_limit((const void*)k_gram<double, MB, 12>, 64000);
+  set_lds_limit((const void*)k_gram<double, MB, 8>, GP_LDS_LIMIT);
+  set_lds_limit((const void*)k_gram<double, MB, 16>, GP_LDS_LIMIT);
+  set_lds_limit((const void*)k_gram<double, MB, 24>, GP_LDS_LIMIT);
   if constexpr (MB <= 8) {
     set_lds_limit((const void*)k_gram_bf16<MB, 8>, 96000);
     set_lds_limit((const void*)k_gram_bf16<MB, 18>, 96000);
@@ -1791,9 +1859,9 @@ static void gram_attrs() {
 template <int MB>
 static void launch_gram_mb(int prec, int pf, dim3 g, size_t lds, hipStream_t s, const GramArgs& ga) {
   if (prec == DG_FP64) {
-    if (pf <= 4) hipLaunchKernelGGL((k_gram<double, MB, 4>), g, dim3(GP_THREADS), lds, s, ga);
-    else if (pf <= 8) hipLaunchKernelGGL((k_gram<double, MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
-    else hipLaunchKernelGGL((k_gram<double, MB, 12>), g, dim3(GP_THREADS), lds, s, ga);
+    if (pf <= 8) hipLaunchKernelGGL((k_gram<double, MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
+    else if (pf <= 16) hipLaunchKernelGGL((k_gram<double, MB, 16>), g, dim3(GP_THREADS), lds, s, ga);
+    else hipLaunchKernelGGL((k_gram<double, MB, 24>), g, dim3(GP_THREADS), lds, s, ga);
   } else if constexpr (MB <= 8) {
     if (pf <= 8) hipLaunchKernelGGL((k_gram_bf16<MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
     else hipLaunchKernelGGL((k_gram_bf16<MB, 18>), g, dim3(GP_THREADS), lds, s, ga);
@@ -1899,7 +1967,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
       maxb = m;
       break;
     }
-  const int pf = prec == DG_FP64 ? (pl.maxnc + 31) / 32 : (pl.maxnc + 15) / 16;
+  const int pf = (pl.maxnc + 15) / 16;   // FP64: 16 columns per pass of 32 rows; BF16: 16 per pass
   const int groups = pl.ntiles;
   // row-range split: row ranges of about 8192 rows of the largest element, and at least
   // 2048 workgroups over the launch (long single ranges leave the launch to a tail of
@@ -1926,7 +1994,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     const double ni = S.nb * ke, nj = T.nb * kt;
     flops += (sym ? r * ni * (ni + 1.0) : 2.0 * r * ni * nj) * (pair ? 2.0 : 1.0);
   }
-  const size_t lds = prec == DG_FP64 ? (size_t)GP_R * (pl.maxnc + 1) * sizeof(double) + (size_t)pl.maxnc * sizeof(void*)
+  const size_t lds = prec == DG_FP64 ? (size_t)GP_RP * pl.maxnc * sizeof(double) + (size_t)pl.maxnc * sizeof(void*)
                                      : (size_t)3 * pl.maxnc * GB_PITCH * 2 + (size_t)pl.maxnc * sizeof(void*);
   auto launch = [&](int ns) -> int {
     ga.nsplit = ns;
