@@ -39,7 +39,12 @@ METRIC = "ALB element-solves/s + Hψ GB/s, mixed vs FP64 on one GPU at 1e-8 Ha e
 # the instrumented step (profiles/*_hbm_traffic.md), scaled by what the counters read
 # for a 1 GiB device copy of the same run.  Valid only for the kernel source and
 # workload they were taken on: `traffic` is reported null once the source differs.
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {
+    # profiles/c4_fp64_hbm_traffic.md: one-stream C4, Gram class (k_gram + k_gram_reduce) per call
+    "gram": {"config": "c4/1", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
+             "sha256": "de2ec5421e5bc477c72b913a3d42fdbc64b7c8cc24630383c5da325d6301a0e8",
+             "bytes_per_launch": 132034714493},
+}
 
 
 def parse():
@@ -54,12 +59,16 @@ def parse():
     ap.add_argument("--no-instrumented", action="store_true", help="skip the per-kernel timing step")
     ap.add_argument("--no-isolated", action="store_true", help="skip the one-stream step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inner-steps", type=int, default=3,
+                    help="timed inner-SCF re-solves (V_eff update + warm start); 0 skips the leg")
     ap.add_argument("--budget-s", type=float, default=520.0,
                     help="wall-clock budget: side legs that would end past it are skipped (and said so)")
     ap.add_argument("--method", default="lobpcg", choices=["lobpcg", "chfsi"])
     ap.add_argument("--cheb-degree", type=int, default=16)
     ap.add_argument("--graph-iters", type=int, default=0,
                     help="LOBPCG steps captured per HIP graph replay (0: launch per kernel)")
+    ap.add_argument("--no-peak-probe", action="store_true",
+                    help="skip the box-measured copy bandwidth and FP64 GEMM rate (context, not the peak used)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (reference for PMC byte counters)")
     return ap.parse_args()
@@ -192,6 +201,94 @@ def cpu_baseline(cfg, tol):
                        f"+ ALB SVD in {dt:.1f} s")}
 
 
+def peak_probe(torch):
+    """What this machine delivers to a plain device copy (1 GiB, read + write) and to a
+    library FP64 GEMM (torch.matmul, 8192^3, rocBLAS): context for the roofline,
+    whose peaks stay the published ones."""
+    n = 1 << 27
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 10
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * 8 * n * reps / (ev[0].elapsed_time(ev[1]) / 1000.0) / 1e9
+    del a, b
+    m = 8192
+    x = torch.randn(m, m, dtype=torch.float64, device="cuda")
+    y = torch.randn(m, m, dtype=torch.float64, device="cuda")
+    z = x @ y
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(3):
+        z = x @ y
+    ev[1].record()
+    torch.cuda.synchronize()
+    tf = 2.0 * m ** 3 * 3 / (ev[0].elapsed_time(ev[1]) / 1000.0) / 1e12
+    del x, y, z
+    # the library at this path's own GEMM shapes: S^T S and S C for the largest and a
+    # middle element of the uneven batch (N, 3K = 262144, 264 and 147456, 165)
+    lib = {}
+    for N, K in ((262144, 88), (147456, 55)):
+        S = torch.randn(3 * K, N, dtype=torch.float64, device="cuda")     # column-major N x 3K
+        Cc = torch.randn(K, 3 * K, dtype=torch.float64, device="cuda")
+        for tag, fn, fl in (("gram", lambda: S @ S.T, 2.0 * N * 9 * K * K), ("rotation", lambda: Cc @ S, 6.0 * N * K * K)):
+            fn()
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(3):
+                fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            lib[f"{tag}_N{N}_3K{3 * K}_TFLOPs"] = round(fl * 3 / (ev[0].elapsed_time(ev[1]) / 1000.0) / 1e12, 2)
+        del S, Cc
+    torch.cuda.empty_cache()
+    return {"copy_GBs": round(copy_gbs, 1), "dgemm_TFLOPs": round(tf, 2), "library_at_path_shapes": lib,
+            "how": ("1 GiB device copy x10 (2 x bytes per copy); torch.matmul FP64 8192^3 x3 and at the "
+                    "path's Gram (S^T S, dense count) and rotation (S C) shapes x3; HIP events")}
+
+
+def smooth_field(el, seed, amp):
+    """Smooth seeded potential change on Q_k: one cosine per axis with random phases."""
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    ax = [np.cos(2 * np.pi * np.arange(n) / n + p) for n, p in zip(el.n, ph)]
+    return amp * (ax[2][:, None, None] * ax[1][None, :, None] * ax[0][None, None, :]).ravel()
+
+
+def run_inner_scf(E, els, D, torch, kw, tol, steps):
+    """Inner SCF as in the paper's flowchart: V_eff changes by a decaying correction
+    (0.05 Ha, then x0.3 per step), and each step re-solves warm-started from the last
+    vectors and regenerates the ALBs.  The potentials are uploaded before the timed
+    region; the original V_eff is restored afterwards."""
+    base = np.concatenate([el.v_eff for el in els])
+    delta = np.concatenate([smooth_field(el, 900 + k, 0.05) for k, el in enumerate(els)])
+    vs = [torch.tensor(base + (0.3 ** s) * delta, dtype=torch.float64, device="cuda") for s in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for s in range(steps):
+        E.set_potential(vs[s])
+        eig, res, it, st = E.solve(None, warm_start=True, **kw)
+        E.make_alb()
+        mr = float(res.max().item())
+        if st != D.DG_OK or not (mr <= tol):
+            raise SystemExit(f"bench.py: inner-SCF step {s} ended with status {D.status_string(st)} and max "
+                             f"residual {mr:.3e}")
+        its.append(float(np.mean(it)))
+        log(f"inner SCF: step {s + 1}/{steps}, mean iterations {its[-1]:.1f}")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    E.set_potential(torch.tensor(base, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    return sec, its
+
+
 def make_x0(cfg, E, D, torch):
     if cfg.name == "c4":
         # 2.3e9 starting values: drawn on the device from a seeded generator
@@ -260,8 +357,12 @@ def main():
     }
     skipped = []
 
-    def have_time(est_s):
-        return time.perf_counter() - t_start + est_s <= args.budget_s
+    # the one-stream step (the headline roofline) and the oracle timing run last and
+    # must fit: every earlier side leg leaves time for them
+    reserve = (0.0 if args.no_isolated else 2.5 * step_s + 15.0) + (0.0 if args.no_cpu_baseline else 60.0)
+
+    def have_time(est_s, keep=reserve):
+        return time.perf_counter() - t_start + est_s + keep <= args.budget_s
 
     if not args.no_mixed:
         kwmx = dict(kw64, precision=D.DG_MIXED)
@@ -277,15 +378,30 @@ def main():
                             "max_resid": rmx["max_resid"]}
         else:
             skipped.append("mixed")
+    if args.inner_steps > 0:
+        if have_time(args.inner_steps * step_s + 10.0):
+            sec, its = run_inner_scf(E, els, D, torch, kw64, args.tol, args.inner_steps)
+            out["inner_scf_fp64"] = {"value": round(n * args.inner_steps / sec, 4), "unit": "element-solves/s",
+                                     "steps": args.inner_steps, "ms_per_step": round(1000.0 * sec / args.inner_steps, 3),
+                                     "iters_mean_per_step": [round(x, 2) for x in its],
+                                     "cold_iters_mean": out["iters_fp64"]["mean"],
+                                     "dv": "smooth seeded correction, 0.05 Ha x 0.3^step"}
+        else:
+            skipped.append("inner_scf")
+
     if not args.no_instrumented and have_time(step_s * 1.3):
         ri = run_instrumented(E, x0, kw64, args.tol, torch, "fp64 instrumented")
         log(f"fp64 instrumented step: {ri['seconds']:.3f} s")
         alg, passes = hpsi_rates(ri)
         out["hpsi_GBs_fp64"] = alg
         out["hpsi_pass_GBs_fp64"] = passes
+        # with element groups on their own streams, kernels of different groups overlap
+        # and every event-timed duration includes the others' share of the GPU: this
+        # table shows where the time goes, the roofline is taken from the one-stream step
         out["kernels_fp64"] = kernel_table(ri)
-        out["roofline"] = roofline_for(ri, cfg.name)
-        out["roofline"]["measured"] = "instrumented FP64 step, element groups sharing the GPU"
+        out["kernels_fp64_note"] = "element groups on 4 streams: durations include overlap with other groups"
+        out["roofline"] = roofline_for(ri, cfg.name, with_traffic=False)
+        out["roofline"]["measured"] = "instrumented FP64 step, element groups sharing the GPU (overlapped)"
         if "mixed" in out and have_time(step_s * 1.2):
             rim = run_instrumented(E, x0, dict(kw64, precision=D.DG_MIXED), args.tol, torch, "mixed instrumented")
             alg, passes = hpsi_rates(rim)
@@ -294,7 +410,7 @@ def main():
     elif not args.no_instrumented:
         skipped.append("instrumented")
     if not args.no_isolated:
-        if have_time(step_s * 2.5):
+        if have_time(step_s * 2.5, keep=0.0 if args.no_cpu_baseline else 60.0):
             # all elements in one stream: kernel durations without overlap between groups
             del E
             torch.cuda.empty_cache()
@@ -304,11 +420,17 @@ def main():
             log(f"one stream: {r1['seconds']:.3f} s")
             alg, passes = hpsi_rates(r1)
             out["one_stream_fp64"] = {"value": round(n / r1["seconds"], 4), "hpsi_GBs": alg,
-                                      "hpsi_pass_GBs": passes, "kernels": kernel_table(r1),
-                                      "roofline": roofline_for(r1, cfg.name, with_traffic=False)}
+                                      "hpsi_pass_GBs": passes, "kernels": kernel_table(r1)}
+            # the headline roofline: kernels one at a time, durations not shared
+            out["roofline"] = roofline_for(r1, cfg.name + "/1")
+            out["roofline"]["measured"] = ("instrumented FP64 step, all elements in one stream (HIP events "
+                                           "on that stream around each launch group)")
             del E1
         else:
             skipped.append("one_stream")
+    if not args.no_peak_probe:
+        out["box_measured"] = peak_probe(torch)
+        log(f"peak probe: {out['box_measured']}")
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, args.tol)

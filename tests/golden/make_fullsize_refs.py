@@ -11,7 +11,10 @@ per element, what the GPU parity tests compare against:
   construction of the "Generating ALB functions" subsection);
 * for the elements named in ALB_ELEMENTS, an orthonormal ALB basis U stored in
   float32 (re-orthonormalised in float64 on load; the rounding moves the span
-  by ~4e-8 rad, far below the 1e-6 rad angle tolerance).
+  by ~4e-8 rad, far below the 1e-6 rad angle tolerance).  These elements are
+  solved to 1e-12: the ALB span amplifies an eigenvector error by 1 / sigma_min
+  of the restriction (down to 6e-7 on this slab), so the angle test needs
+  eigenvectors well inside the 1e-6 rad it asserts.
 
 Output: tests/golden/fullsize/<config>_oracle.json and
 <config>_e<k>_alb_f32.npy.  Usage:
@@ -38,22 +41,23 @@ from oracle import lobpcg as olob  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fullsize")
 TOL = 1e-10
+TOL_ALB = 1e-12
 # elements whose ALB basis is stored (the angle tests); the other elements keep
 # eigenvalues, residuals, gaps and singular values only
 ALB_ELEMENTS = {"c2": (0, 9, 10, 11), "c3": (0,), "c4": ()}
 
 
-def solve_element(cfg, k):
+def solve_element(cfg, k, tol):
     el = cfg.elements[k]
     J = el.n_states
     g = W.guard_count(J)
     x0 = W.initial_block(el.npts, J + g, cfg.x0_seed_base + k).T
     t0 = time.perf_counter()
-    r = olob.lobpcg(el, x0, J, tol=TOL, max_iter=600)
+    r = olob.lobpcg(el, x0, J, tol=tol, max_iter=800)
     dt = time.perf_counter() - t0
     U, s = oalb.make_alb(el, r.X, J)
     rec = {
-        "grid": list(el.n), "n_states": J, "n_guard": g, "iters": int(r.iters),
+        "grid": list(el.n), "n_states": J, "n_guard": g, "tol": tol, "iters": int(r.iters),
         "converged": bool(r.converged), "seconds": round(dt, 1),
         "eigvals": [float(v) for v in r.eigvals],
         "resid": [float(v) for v in r.resid],
@@ -74,7 +78,7 @@ def main(argv):
         with open(path) as f:
             data = json.load(f)
     for k in ks:
-        rec, U = solve_element(cfg, k)
+        rec, U = solve_element(cfg, k, TOL_ALB if k in ALB_ELEMENTS.get(name, ()) else TOL)
         data["elements"][str(k)] = rec
         if k in ALB_ELEMENTS.get(name, ()):
             np.save(os.path.join(OUT, f"{name}_e{k}_alb_f32.npy"), U.astype(np.float32))

@@ -61,3 +61,28 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert p.stdout.strip() == ""
     with pytest.raises(json.JSONDecodeError):
         json.loads(p.stdout or "x")
+
+
+def test_hpsi_rates_use_the_per_state_count_and_the_pass_bytes():
+    """The algorithmic H*psi rate divides the per-state count (2Ns + Ns/J + nnz(s+4)/J,
+    summed by the library) by the three H*psi classes' time; the pass rate their own
+    bytes by the same time; a run without H*psi time reports none."""
+    n = len(bench.CLASSES)
+    r = {"ms": [2.0, 1.0, 1.0] + [5.0] * (n - 3), "work": [1e9, 2e9, 1e9] + [7.0] * (n - 3),
+         "hpsi_alg_bytes": 2e9}
+    alg, passes = bench.hpsi_rates(r)
+    assert alg == pytest.approx(2e9 / 4e-3 / 1e9, rel=1e-3)
+    assert passes == pytest.approx(4e9 / 4e-3 / 1e9, rel=1e-3)
+    r0 = dict(r, ms=[0.0, 0.0, 0.0] + [5.0] * (n - 3))
+    assert bench.hpsi_rates(r0) == (None, None)
+
+
+def test_inner_scf_correction_is_smooth_and_decays():
+    import numpy as np
+    import workloads as W
+    el = W.small_slab(n_states=8)[0]
+    d = bench.smooth_field(el, 3, 0.05)
+    assert d.shape == (el.npts,) and np.max(np.abs(d)) <= 0.05 + 1e-15
+    # one cosine per axis: the 3D DFT has 8 nonzero coefficients (+-1 per axis)
+    F = np.fft.fftn(d.reshape(el.n[2], el.n[1], el.n[0]))
+    assert np.sum(np.abs(F) > 1e-9 * np.abs(F).max()) == 8

@@ -11,13 +11,19 @@ What is compared:
 * every eigenvalue of every referenced element, |lambda_gpu - lambda_oracle| <=
   1e-8 Ha, for the FP64 and the mixed-precision paths (the J lowest: an eigenvalue
   missed below lambda_J would shift the comparison by a whole level);
-* ALB subspaces by their largest principal angle.  The angle is set by the gap at
-  the cut: by Davis-Kahan each solution's eigenvector block lies within
-  ||R|| / gap of the invariant subspace (R the residual block: <= 1e-10 on both
-  sides here).  Where the gap is at least 1e-3 Ha that bound is below 2e-7 and the
-  ALB angle must be <= 1e-6 rad; at smaller gaps (near-degenerate cuts, where the
-  ALB span is barely determined) it must stay within 10x the bound.  Gaps, bounds
-  and the smallest singular value of the restriction are printed.
+* ALB subspaces.  By Davis-Kahan each solution's eigenvector block lies within
+  DK = ||R|| / gap of the invariant subspace (R the residual block; the oracle's
+  references of these elements are solved to 1e-12, the GPU to 1e-10, its FP64
+  residual floor on these 147,456-point blocks lying near 5e-11).  Two measures:
+  - the restricted projector U S^2 U^T = R_E X X^T R_E^T, which moves by at most
+    about 2 DK whatever the conditioning: its difference must be <= 10 DK + 5e-7
+    (the float32 storage of the reference basis);
+  - the largest principal angle between the ALB spans, which the restriction can
+    amplify by up to 1 / sigma_min (sigma_min reaches 6e-7 here: the direction of
+    the smallest singular value is the least determined).  Where the gap is at
+    least 1e-3 Ha and DK / sigma_min <= 1e-7 the angle must be <= 1e-6 rad; else it
+    must stay within 10 DK / sigma_min (or 1e-6).  Gaps, bounds and sigma_min are
+    printed.
 """
 import json
 import os
@@ -63,6 +69,8 @@ def _solve(els, ks, seed_base, precision, tol):
                                                       + W.guard_count(els[k].n_states), seed_base + k).ravel()
                                       for k in ks]), dtype=torch.float64, device="cuda")
     eig, res, iters, st = E.solve(x0, precision=precision, tol=tol)
+    print(f"[fullsize] status {st}, max residual {res.max().item():.2e} (tol {tol:g}), iterations "
+          f"{iters.min()}..{iters.max()}", flush=True)
     assert st == 0, st
     off = E.offsets(D.DG_OFF_EIG)
     ev = eig.cpu().numpy()
@@ -123,23 +131,31 @@ def _angle_case(name, ks_all, tol_gpu):
         r = refs["elements"][str(k)]
         J = r["n_states"]
         U = _alb_ref(name, k)
+        s_ref = np.array(r["sigma"])
+        s_gpu = sv.cpu().numpy()[E.offsets(D.DG_OFF_EIG)[i]:E.offsets(D.DG_OFF_EIG)[i + 1]]
         ang = oalb.max_principal_angle(U, A[i])
-        smin = min(r["sigma"])
-        bound = (float(res[i * J:(i + 1) * J].max()) + max(r["resid"][:J])) / r["gap"]
-        print(f"{name} element {k}: ALB angle {ang:.2e} rad, gap {r['gap']:.2e} Ha, sigma_min {smin:.2e}, "
-              f"Davis-Kahan bound {bound:.1e}", flush=True)
-        if r["gap"] >= 1e-3:
+        smin = float(min(r["sigma"]))
+        dk = (float(res[i * J:(i + 1) * J].max()) + max(r["resid"][:J])) / r["gap"]
+        # || A S_g^2 A^T - U S_o^2 U^T ||_2 on span[A, U] (2J x 2J)
+        Q, _ = np.linalg.qr(np.hstack([A[i], U]))
+        Ag, Uo = Q.T @ (A[i] * s_gpu), Q.T @ (U * s_ref)
+        dproj = float(np.max(np.abs(np.linalg.eigvalsh(Ag @ Ag.T - Uo @ Uo.T))))
+        print(f"{name} element {k}: restricted projector difference {dproj:.1e} (bound {10 * dk + 5e-7:.1e}); "
+              f"ALB angle {ang:.2e} rad, gap {r['gap']:.2e} Ha, sigma_min {smin:.2e}, Davis-Kahan {dk:.1e} "
+              f"(over sigma_min {dk / smin:.1e}); oracle tol {r.get('tol', refs['tol']):g}", flush=True)
+        assert dproj <= 10 * dk + 5e-7
+        if r["gap"] >= 1e-3 and dk / smin <= 1e-7:
             n_tight += 1
             assert ang <= 1e-6
         else:
-            assert ang <= max(1e-6, 10.0 * bound)
+            assert ang <= max(1e-6, 10.0 * dk / smin)
     return n_tight
 
 
 def test_c2_alb_subspaces():
     """Stored ALB bases of the 4x4 slab: the GPU solves those elements to 1e-10."""
     n_tight = _angle_case("c2", range(16), 1e-10)
-    print(f"{n_tight} element(s) with a gap >= 1e-3 Ha (angle asserted <= 1e-6 rad)")
+    print(f"{n_tight} element(s) where the angle is asserted <= 1e-6 rad")
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -155,3 +171,48 @@ def test_c3_elements_eigenvalues(precision):
 
 def test_c3_alb_subspaces():
     _angle_case("c3", range(64), 1e-10)
+
+
+def _smooth_field(el, seed, amp):
+    """A smooth seeded potential change on Q_k: a product of one cosine per axis with
+    random phases (an inner-SCF correction of amplitude amp, Ha)."""
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    ax = [np.cos(2 * np.pi * np.arange(n) / n + p) for n, p in zip(el.n, ph)]
+    return amp * (ax[2][:, None, None] * ax[1][None, :, None] * ax[0][None, None, :]).ravel()
+
+
+def test_c2_inner_scf_warm_resolves_reach_the_oracle():
+    """Inner SCF at full size (Fig. 2: the ALBs follow V_eff): the 4x4 slab is solved
+    cold at a displaced potential V + delta, then V_eff steps back to V through
+    V + 0.3 delta and V, each step a set_potential and a warm-started re-solve.  The
+    last re-solve must reach the oracle's stored eigenvalues at V (every element,
+    <= 1e-8 Ha), and the warm re-solves take fewer iterations than the cold one."""
+    torch = need_torch_cuda()
+    from paper_2003_00407_amd import dgalb as D
+    import dataclasses
+    refs = _refs("c2")
+    cfg = W.make_config("c2")
+    els = cfg.elements
+    deltas = [_smooth_field(el, 500 + k, 0.05) for k, el in enumerate(els)]
+    start = [dataclasses.replace(el, v_eff=el.v_eff + d) for el, d in zip(els, deltas)]
+    E = D.Elements(start)
+    x0 = torch.tensor(D.pack_initial(els, cfg.x0_seed_base), dtype=torch.float64, device="cuda")
+    print("[inner-scf] cold solve at V + delta", flush=True)
+    _, _, it_cold, st = E.solve(x0, tol=1e-8)
+    assert st == 0
+    its = []
+    for scale in (0.3, 0.0):
+        v = np.concatenate([el.v_eff + scale * d for el, d in zip(els, deltas)])
+        E.set_potential(torch.tensor(v, dtype=torch.float64, device="cuda"))
+        eig, res, it, st = E.solve(None, tol=1e-8, warm_start=True)
+        assert st == 0 and res.max().item() <= 1e-8
+        its.append(it)
+        print(f"[inner-scf] V + {scale} delta: warm re-solve iterations mean {it.mean():.1f} "
+              f"(cold {it_cold.mean():.1f})", flush=True)
+    off = E.offsets(D.DG_OFF_EIG)
+    ev = eig.cpu().numpy()
+    _check_eigs("c2", refs, list(range(16)), [ev[off[k]:off[k + 1]] for k in range(16)], its[-1],
+                "inner-scf warm")
+    alb, sv = E.make_alb()
+    assert all(it.sum() < it_cold.sum() for it in its)
