@@ -48,6 +48,22 @@ __device__ __forceinline__ const T* vcol(const ElemDev& E, const ColSet& s, int 
   return reinterpret_cast<const T*>(E.blk[s.blk[b]]) + (size_t)(c - b * K) * E.ld;
 }
 
+// Loads through a global-address-space pointer: the block pointers come from tables
+// in memory, so the compiler cannot infer the address space and would otherwise use
+// flat loads, which also count against the LDS counter and get conservative waits.
+typedef double gd2 __attribute__((ext_vector_type(2)));
+template <typename V>
+__device__ __forceinline__ V gload(const void* p) {
+  return *(const __attribute__((address_space(1))) V*)(p);
+}
+__device__ __forceinline__ double2 gload2(const void* p) {
+  const gd2 v = *(const __attribute__((address_space(1))) gd2*)(p);
+  return double2{v.x, v.y};
+}
+__device__ __forceinline__ void gstore2(void* p, double x, double y) {
+  *(__attribute__((address_space(1))) gd2*)(p) = gd2{x, y};
+}
+
 // ---------------------------------------------------------------------------
 // Gram: part[e][split][i][j] = sum_{r in split} S[r,i] T[r,j]
 //
@@ -1236,7 +1252,7 @@ constexpr int RT_NCT = RT_MAXC / 16;
 constexpr int RT_CP = RT_CC + 2;
 
 template <typename T, int NCT>
-__global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs A) {
+__global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 3 : 2) k_rotate(RotArgs A) {
   static_assert(sizeof(T) == 8 && RT_RT == 2, "FP64 rotation with two interleaved row tiles per lane");
   const int e = blockIdx.y;
   const ElemDev& E = A.elems[e];
@@ -1276,27 +1292,36 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
       lo = c0[0];
       hi = c1[0];
     }
-    // S values of the next C chunk are loaded while the current one is multiplied
+    // S values of the next C chunk are loaded while the current one is multiplied.
+    // The (at most three) block bases of S are resolved once: a per-column lookup of
+    // the block table would put a dependent pointer load before every column load.
+    const T* sb0 = reinterpret_cast<const T*>(E.blk[A.S.blk[0]]);
+    const long long d1 = A.S.nb > 1 ? reinterpret_cast<const T*>(E.blk[A.S.blk[1]]) - sb0 : 0;
+    const long long d2 = A.S.nb > 2 ? reinterpret_cast<const T*>(E.blk[A.S.blk[2]]) - sb0 : 0;
+    const long long ldS = E.ld;
+    auto scol = [&](int c) -> const T* {
+      const bool in1 = c >= kS, in2 = c >= 2 * kS;
+      const long long off = (in2 ? d2 : (in1 ? d1 : 0LL)) + (long long)(c - (in2 ? 2 * kS : (in1 ? kS : 0))) * ldS;
+      return sb0 + off;
+    };
     double av[RT_CC / 4][RT_RT], an[RT_CC / 4][RT_RT];
+    // branch-free: every lane loads one 16-byte pair from a valid address (the column
+    // clamped to lo, the row pair to 0; a lone last row's partner lies inside the
+    // leading dimension, which is even and at least N + 1 for odd N) and zeroes what
+    // is out of range
     auto load_s = [&](int cb, double (&dst)[RT_CC / 4][RT_RT]) {
 #pragma unroll
       for (int ks = 0; ks < RT_CC / 4; ++ks) {
         const int c = cb + kl * (RT_CC / 4) + ks;
-        const T* col = c < hi ? vcol<T>(E, A.S, c, kS) : nullptr;
-        double x0 = 0.0, x1 = 0.0;
-        if (col && in1) {
-          const double2 v = *reinterpret_cast<const double2*>(col + rr0);
-          x0 = v.x;
-          x1 = v.y;
-        } else if (col && in0) {
-          x0 = double(col[rr0]);
-        }
-        dst[ks][0] = x0;
-        dst[ks][1] = x1;
+        const bool cin = c < hi;
+        const T* col = scol(cin ? c : lo);
+        const double2 v = gload2(col + (in0 ? rr0 : 0));
+        dst[ks][0] = (cin && in0) ? v.x : 0.0;
+        dst[ks][1] = (cin && in1) ? v.y : 0.0;
       }
     };
     // with six column tiles (two waves per SIMD, registers to spare) the C rows of the
-    // next chunk are prefetched into registers as well; with three (four waves per
+    // next chunk are prefetched into registers as well; with three (three waves per
     // SIMD) they are read when staged
     constexpr bool kPrefC = NCT > 3;
     constexpr int CPT = kPrefC ? (RT_CC * NCT * 16 + RT_THREADS - 1) / RT_THREADS : 1;
@@ -1307,7 +1332,9 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
         const int idx = threadIdx.x + u * RT_THREADS;
         const int cc = idx / (NCT * 16), j = idx % (NCT * 16);
         const int c = cb + cc;
-        cn[u] = (idx < RT_CC * NCT * 16 && c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        const bool ok = idx < RT_CC * NCT * 16 && c < hi && j < ncol;
+        const double v = gload<double>(Cm + (ok ? (size_t)c * cld + j : 0));
+        cn[u] = ok ? v : 0.0;
       }
     };
     if (lo < hi) {
@@ -1370,11 +1397,11 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate(RotArgs
         if (in1) {
           double2 v = {A.alpha * acc[0][t][q], A.alpha * acc[1][t][q]};
           if (beta != 0.0) {
-            const double2 prev = *reinterpret_cast<const double2*>(p);
+            const double2 prev = gload2(p);
             v.x += beta * prev.x;
             v.y += beta * prev.y;
           }
-          *reinterpret_cast<double2*>(p) = v;
+          gstore2(p, v.x, v.y);
         } else if (in0) {
           const double prev = beta != 0.0 ? beta * double(*p) : 0.0;
           *p = T(prev + A.alpha * acc[0][t][q]);
