@@ -98,7 +98,7 @@ struct GramArgs {
 };
 
 constexpr int GP_THREADS = 512;
-constexpr int GP_R = 32;        // grid rows staged per step
+constexpr int GP_R = 16;        // grid rows staged per step
 constexpr int GP_MAXCOL = 384;  // staged columns per workgroup (tiles are chosen to fit)
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -199,13 +199,16 @@ __device__ __forceinline__ GramItem gram_item(const GramArgs& A) {
   return it;
 }
 
-// FP64 staging: column-major panels, GP_RP doubles per staged column (32 rows + 2 pad;
-// about 105 KB for 384 columns, one workgroup per CU).  Lane l reads rows 8 (l / 16) ..
-// 8 (l / 16) + 7 of column (l % 16) of a 16-column fragment as four 16-byte loads;
-// with a column pitch of 272 bytes any 8 (or 16) consecutive lanes of such a load fall
-// on distinct banks.  MFMA k-step j takes row 8 (l / 16) + j from every lane group: the
-// eight k-steps cover the 32 rows of the panel, the same assignment for both operands
-// (a Gram sums over rows in any order).
+// FP64 staging: column-major panels, GP_RP doubles per staged column (16 rows + 2 pad;
+// about 57 KB for 384 columns).  Lane l reads rows 4 (l / 16) .. 4 (l / 16) + 3 of
+// column (l % 16) of a 16-column fragment as two 16-byte loads.  MFMA k-step j takes
+// row 4 (l / 16) + j from every lane group: the four k-steps cover the 16 rows of the
+// panel, the same assignment for both operands (a Gram sums over rows in any order).
+// Occupancy decides the rate: with at most 6 output blocks per wave (<= 128 VGPRs)
+// and 16-row panels two workgroups share a CU and one's barrier and load waits
+// overlap the other's matrix work (measured on the C4 batch in one stream: 26.2
+// TFLOP/s with 12 blocks, 32-row panels and one workgroup per CU; 35.2 with this;
+// 34.9 with three workgroups per CU at 4 blocks).
 constexpr int GP_RP = GP_R + 2;
 constexpr int GP_LDS_LIMIT = 120000;
 
@@ -221,7 +224,7 @@ __device__ __forceinline__ void gram_run_block(const GramTile& g, int bprime, in
 
 // PF: staged values per thread and step (32 columns per pass of the workgroup)
 template <typename T, int MAXB, int PF>
-__global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
+__global__ void __launch_bounds__(GP_THREADS, MAXB <= 6 ? 4 : 2) k_gram(GramArgs A) {
   const GramItem item = gram_item(A);
   if (!item.valid) return;
   const int e = item.e;
@@ -296,7 +299,9 @@ __global__ void __launch_bounds__(GP_THREADS) k_gram(GramArgs A) {
       double v = 0.0;
       if (c < nc) {
         const T* ptr = cp[c];
-        if (ptr && rr < r1) v = double(ptr[rr]);
+        // a global load: a flat load would also count against the LDS counter, and
+        // the fragment reads' waits would then wait for this prefetch as well
+        if (ptr && rr < r1) v = double(gload<T>(ptr + rr));
       }
       pre[u] = v;
     }
@@ -1980,7 +1985,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   }
   const int bj_max = (maxnj + 15) / 16;
   // FP64: up to 12 blocks per wave (16 spill registers) and 384 staged columns; BF16x3: 8 and 288
-  const int cap_blocks = prec == DG_FP64 ? 12 : 8;
+  const int cap_blocks = prec == DG_FP64 ? 6 : 8;
   const int cap_cols = prec == DG_FP64 ? GP_MAXCOL : 288;
   const GramPlan pl = plan_gram_tiles(bis, bj_max, sym, same ? 1 : 0, pair ? 1 : 0, cap_blocks, cap_cols);
   if (pl.maxblk == 0) {
@@ -1994,7 +1999,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
       maxb = m;
       break;
     }
-  const int pf = (pl.maxnc + 15) / 16;   // FP64: 16 columns per pass of 32 rows; BF16: 16 per pass
+  // staged values per thread: FP64 GP_THREADS / GP_R columns per pass; BF16: 16 per pass
+  const int pf = prec == DG_FP64 ? (pl.maxnc + GP_THREADS / GP_R - 1) / (GP_THREADS / GP_R) : (pl.maxnc + 15) / 16;
   const int groups = pl.ntiles;
   // row-range split: row ranges of about 8192 rows of the largest element, and at least
   // 2048 workgroups over the launch (long single ranges leave the launch to a tail of
