@@ -378,7 +378,7 @@ __device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint
 
 // PF: staged values per thread and stage (16 columns per pass of the workgroup)
 template <int MAXB, int PF>
-__global__ void __launch_bounds__(GP_THREADS) k_gram_bf16(GramArgs A) {
+__global__ void __launch_bounds__(GP_THREADS, MAXB <= 6 && PF <= 8 ? 4 : 2) k_gram_bf16(GramArgs A) {
   const GramItem item = gram_item(A);
   if (!item.valid) return;
   const int e = item.e;
@@ -1985,8 +1985,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   }
   const int bj_max = (maxnj + 15) / 16;
   // FP64: up to 12 blocks per wave (16 spill registers) and 384 staged columns; BF16x3: 8 and 288
-  const int cap_blocks = prec == DG_FP64 ? 6 : 8;
-  const int cap_cols = prec == DG_FP64 ? GP_MAXCOL : 288;
+  const int cap_blocks = prec == DG_FP64 ? 6 : 6;
+  const int cap_cols = prec == DG_FP64 ? GP_MAXCOL : 128;
   const GramPlan pl = plan_gram_tiles(bis, bj_max, sym, same ? 1 : 0, pair ? 1 : 0, cap_blocks, cap_cols);
   if (pl.maxblk == 0) {
     set_error("Gram: no tile fits the per-workgroup limits");
