@@ -42,8 +42,8 @@ METRIC = "ALB element-solves/s + Hψ GB/s, mixed vs FP64 on one GPU at 1e-8 Ha e
 PMC_TRAFFIC = {
     # profiles/c4_fp64_hbm_traffic.md: one-stream C4, Gram class (k_gram + k_gram_reduce) per call
     "gram": {"config": "c4/1", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-             "sha256": "de2ec5421e5bc477c72b913a3d42fdbc64b7c8cc24630383c5da325d6301a0e8",
-             "bytes_per_launch": 132034714493},
+             "sha256": "ca4295431753767b75dcba0af5e029d71fdba3562e03ce4f51ef1b570d04c090",
+             "bytes_per_launch": 186360685698},
 }
 
 

@@ -1471,14 +1471,31 @@ __global__ void __launch_bounds__(RT_THREADS, 2) k_rotate_bf16(RotArgs A) {
     }
     // S values of the next step (columns cb + 8 kl + i, rows rrow[u]) are loaded
     // while the current step is multiplied
+    // block bases resolved once (a per-column lookup of the block table puts a
+    // dependent pointer load before every column load); branch-free global loads from
+    // clamped valid addresses, out-of-range values zeroed
+    const float* sb0 = reinterpret_cast<const float*>(E.blk[A.S.blk[0]]);
+    const long long d1 = A.S.nb > 1 ? reinterpret_cast<const float*>(E.blk[A.S.blk[1]]) - sb0 : 0;
+    const long long d2 = A.S.nb > 2 ? reinterpret_cast<const float*>(E.blk[A.S.blk[2]]) - sb0 : 0;
+    const long long ldS = E.ld;
+    auto scol = [&](int c) -> const float* {
+      const bool b1 = c >= kS, b2 = c >= 2 * kS;
+      const long long off = (b2 ? d2 : (b1 ? d1 : 0LL)) + (long long)(c - (b2 ? 2 * kS : (b1 ? kS : 0))) * ldS;
+      return sb0 + off;
+    };
     float sv[RT_RT][8], sn[RT_RT][8];
     auto load_s = [&](int cb, float (&dst)[RT_RT][8]) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int c = cb + 8 * kl + i;
-        const float* col = c < hi ? vcol<float>(E, A.S, c, kS) : nullptr;
+        const bool cin = c < hi;
+        const float* col = scol(cin ? c : lo);
 #pragma unroll
-        for (int u = 0; u < RT_RT; ++u) dst[u][i] = (col && rrow[u] < nrows) ? col[rrow[u]] : 0.f;
+        for (int u = 0; u < RT_RT; ++u) {
+          const bool ok = cin && rrow[u] < nrows;
+          const float v = gload<float>(col + (rrow[u] < nrows ? rrow[u] : 0));
+          dst[u][i] = ok ? v : 0.f;
+        }
       }
     };
     // with six column tiles the C rows of the next step are prefetched into registers
@@ -1492,7 +1509,11 @@ __global__ void __launch_bounds__(RT_THREADS, 2) k_rotate_bf16(RotArgs A) {
         const int idx = threadIdx.x + u * RT_THREADS;
         const int j = idx % (NCT * 16), k = idx / (NCT * 16);
         const int c = cb + k;
-        if constexpr (kPrefC) cn[u] = (idx < RB_K * NCT * 16 && c < hi && j < ncol) ? Cm[(size_t)c * cld + j] : 0.0;
+        if constexpr (kPrefC) {
+          const bool ok = idx < RB_K * NCT * 16 && c < hi && j < ncol;
+          const double v = gload<double>(Cm + (ok ? (size_t)c * cld + j : 0));
+          cn[u] = ok ? v : 0.0;
+        }
       }
     };
     if (lo < hi) {
