@@ -223,6 +223,7 @@ struct Ctx {
   double* dev_bounds = nullptr;    // band energy: (a, b, a0) per element
   double* dev_de = nullptr;        // band energy backward: dE per element
   double* dev_minpiv = nullptr;    // diagnostics: smallest scaled overlap pivot of the last RR
+  int* dev_hpflag = nullptr;       // per element: the last RR's basis is ill-conditioned (H P afresh)
   std::vector<double> be_bounds_host, be_de_host;
   int n_extra_blocks = 0;
   long long* dev_off_x0 = nullptr; // packed offsets (doubles), per element
@@ -246,6 +247,7 @@ struct Ctx {
   int gram_max_split = 16;
   std::map<long long, int> gram_split_table;   // autotuned row splits per Gram shape
   bool autotune = true;
+  bool fresh_hp_all = false;                   // DG_FRESH_HP=1: HP = H P for every element each LOBPCG step
   bool orth_w = false;                         // W <- W - X (X^T W) before the projected problem
                                                // (DG_ORTH_W=1); by default the overlap S^T S carries it                        // DG_TUNE=0 keeps the default splits
   int nl_pending_np = 0, nl_pending_kk = 0;
@@ -255,6 +257,8 @@ struct Ctx {
   double rr_pivot_tol = 1e-13;     // overlap-Cholesky breakdown threshold (FP64 data)
   double rr_drop_tol = 1e-8;       // W/P columns with smaller scaled overlap pivots leave the basis
   double rr_drop_env = -1.0;       // DG_RR_DROP override (diagnostics)
+  double hp_tol = 1e-6;            // scaled overlap pivots below this: H P applied afresh, not rotated
+  double hp_tol_env = -1.0;        // DG_HP_TOL override
   double rr_ortol = 1e-5;          // cluster tolerance of the inverse iteration (relative to ||T||)
   long long* dev_phase = nullptr;  // diagnostics: RR phase timestamps (16 per element)
 };

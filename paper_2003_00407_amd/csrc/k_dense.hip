@@ -634,6 +634,10 @@ struct RRArgs {
   double* minpiv;        // optional: smallest scaled pivot, its column, dropped count (diagnostics)
   double ortol;          // eigenvalues closer than ortol * ||T|| are treated as one cluster
   int lds_dyn;           // dynamic LDS bytes of the launch (LDS variant)
+  int* hp_flag;          // optional, per element: 1 when the smallest scaled pivot is below hp_tol
+                         // (the rotated H P' would carry cancellation error), 0 otherwise and
+                         // for inactive elements
+  double hp_tol;
 };
 
 constexpr int kRRThreads = 512;
@@ -664,7 +668,10 @@ template <bool kLds>
 __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   const int e = blockIdx.x;
   const ElemDev& E = A.elems[e];
-  if (A.active && !A.active[e]) return;
+  if (A.active && !A.active[e]) {
+    if (A.hp_flag && threadIdx.x == 0) A.hp_flag[e] = 0;
+    return;
+  }
   const int K = E.K;
   const bool gen = A.mode == RR_GEN, svd = A.mode == RR_SVD;
   const int n = gen ? A.nb * K : kcode(A.kfix, E);
@@ -768,6 +775,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     if (lane == 0) row[j] = u;
   }
   __syncthreads();
+  if (A.hp_flag && tid == 0) A.hp_flag[e] = (brk || !(pmin >= A.hp_tol)) ? 1 : 0;
   if (A.minpiv && tid == 0) {
     A.minpiv[3 * e] = pmin;
     A.minpiv[3 * e + 1] = jmin;
@@ -2174,7 +2182,7 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
   RRArgs a{c.elems_dev, active, nb, kfix, nkeep, mode, c.dev_status,
            c.log_level >= 2 ? c.dev_phase : nullptr, c.gram_part, c.gram_part_stride,
            c.rr_pivot_tol, c.rr_drop_tol, c.log_level >= 3 ? c.dev_minpiv : nullptr, c.rr_ortol,
-           in_lds ? (int)need : 0};
+           in_lds ? (int)need : 0, mode == RR_GEN ? c.dev_hpflag : nullptr, c.hp_tol};
   TimedScope ts(c, TC_RR, flops);
   if (in_lds) {
     hipLaunchKernelGGL(k_rr_lds<true>, dim3(c.n_elem), dim3(kRRThreads), need, c.stream, a);

@@ -137,7 +137,7 @@ struct Plan {
   std::vector<ElemPlan> el;
   size_t off_elems, off_iota, off_active, off_status, off_count, off_iters, off_maxres, off_phase, off_bounds,
       off_de,
-      off_minpiv;
+      off_minpiv, off_hpflag;
   int n_extra;
   size_t off_offx0, off_offvec, off_offalb, off_offgrid, off_offeig, off_offkall, off_offelem, off_offjj,
       off_nprojoff, off_lists;
@@ -288,6 +288,7 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   P.off_bounds = take(sizeof(double) * 3 * n_elem);
   P.off_de = take(sizeof(double) * n_elem);
   P.off_minpiv = take(3 * sizeof(double) * n_elem);
+  P.off_hpflag = take(sizeof(int) * n_elem);
   P.off_offx0 = take(sizeof(long long) * (n_elem + 1));
   P.off_offvec = take(sizeof(long long) * (n_elem + 1));
   P.off_offalb = take(sizeof(long long) * (n_elem + 1));
@@ -383,6 +384,8 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   if (const char* dt = std::getenv("DG_RR_DROP")) c->rr_drop_env = std::atof(dt);
   if (const char* tu = std::getenv("DG_TUNE")) c->autotune = std::atoi(tu) != 0;
   if (const char* ow = std::getenv("DG_ORTH_W")) c->orth_w = std::atoi(ow) != 0;
+  if (const char* fh = std::getenv("DG_FRESH_HP")) c->fresh_hp_all = std::atoi(fh) != 0;
+  if (const char* ht = std::getenv("DG_HP_TOL")) c->hp_tol_env = std::atof(ht);
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {
@@ -587,6 +590,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   c->dev_bounds = (double*)(A + P.off_bounds);
   c->dev_de = (double*)(A + P.off_de);
   c->dev_minpiv = (double*)(A + P.off_minpiv);
+  c->dev_hpflag = (int*)(A + P.off_hpflag);
   c->n_extra_blocks = P.n_extra;
   c->dev_phase = (long long*)(A + P.off_phase);
   c->dev_maxres = (double*)(A + P.off_maxres);

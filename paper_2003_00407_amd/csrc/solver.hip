@@ -97,15 +97,31 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   ra.ncol = KC_K;
   ra.c_blockrows = 1;
   if ((st = launch_rotate(c, prec, ra))) return st;
-  // X, P are free now: HX' = HS C goes to X; HP' = H P' is applied afresh into P,
-  // so that S^T H S stays consistent with S in the nearly dependent directions
-  // of P (a rotated HP drifts from H P there)
-  const bool fresh_hp = ra.nout == 2;
+  // X, P are free now: HX' = HS C goes to X and HP' = [HW HP] C_WP to P.  Where the
+  // basis was nearly dependent (a scaled overlap pivot below hp_tol), C_WP combines
+  // large coefficients that cancel, and the rotated HP' drifts from H P' by the
+  // rounding of that cancellation; for those elements (flagged by the Rayleigh-Ritz
+  // kernel) HP' = H P' is applied afresh, so that S^T H S stays consistent with S
+  const bool two = ra.nout == 2;
   ra.S = HS;
-  ra.nout = 1;
   ra.out_blk[0] = B_X;
+  ra.out_blk[1] = B_P;
   if ((st = launch_rotate(c, prec, ra))) return st;
-  if (fresh_hp && (st = launch_hpsi(c, -1, 0, prec, B_T1, B_P, active))) return st;
+  if (two) {
+    const int* mask = (c.fresh_hp_all || !c.dev_hpflag) ? active : c.dev_hpflag;
+    std::vector<int> saved;
+    const bool account = mask == c.dev_hpflag && c.timing && !c.capturing;
+    if (account) {
+      // per-kernel byte accounting counts the flagged elements only
+      std::vector<int> fl(c.n_elem);
+      if ((st = sync_read(c, fl.data(), c.dev_hpflag, sizeof(int) * c.n_elem))) return st;
+      saved = c.active_host;
+      c.active_host = fl;
+    }
+    st = launch_hpsi(c, -1, 0, prec, B_T1, B_P, mask);
+    if (account) c.active_host = saved;
+    if (st) return st;
+  }
   // new X = T0, P = T1, HX = X, HP = P, T0 = HX, T1 = HP
   int perm[kMaxBlocks] = {B_T0, B_W, B_T1, B_X, B_HW, B_P, B_HX, B_HP};
   return launch_permute(c, perm, active);
@@ -148,6 +164,7 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
   // matrix is then accurate to about eps * ||H|| / drop_tol in the worst kept direction.
   c.rr_pivot_tol = (prec == DG_FP64) ? 1e-13 : 1e-6;
   c.rr_drop_tol = c.rr_drop_env >= 0.0 ? c.rr_drop_env : (prec == DG_FP64 ? 1e-8 : 1e-4);
+  c.hp_tol = c.hp_tol_env >= 0.0 ? c.hp_tol_env : (prec == DG_FP64 ? 1e-6 : 1e-3);
   if ((st = reset_breakdowns(c))) return st;
   if ((st = launch_hpsi(c, -1, 0, prec, B_X, B_HX, active))) return st;
   // (the start rotation leaves the block in T1 as P: a carried search direction)

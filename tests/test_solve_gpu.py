@@ -115,7 +115,10 @@ def test_c2_full_size_certificate():
 
 @pytest.mark.parametrize("J", [7, 19])
 def test_free_electron_shells_vs_golden(J):
-    """v = 0 in the 10 bohr cube: eigenvalues are the closed-form |G|^2/2 shells (degenerate)."""
+    """v = 0 in the 10 bohr cube: eigenvalues are the closed-form |G|^2/2 shells (degenerate).
+    Near convergence the basis [X W P] of the J = 19 case becomes nearly dependent (scaled
+    pivots ~1e-8): a rotated HP diverges there, so this also checks that such elements
+    get H P applied afresh."""
     import os
     rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "free_electron_10bohr_16cubed.txt"))
     expect = np.concatenate([np.full(int(m), v) for _, v, m, _ in rows])[:J]
