@@ -247,6 +247,7 @@ struct Ctx {
   int gram_max_split = 16;
   std::map<long long, int> gram_split_table;   // autotuned row splits per Gram shape
   bool autotune = true;
+  bool bf16 = false;                           // DG_BF16=1: FP32 blocks' Grams and rotations as BF16x3
   bool fresh_hp_all = false;                   // DG_FRESH_HP=1: HP = H P for every element each LOBPCG step
   bool orth_w = false;                         // W <- W - X (X^T W) before the projected problem
                                                // (DG_ORTH_W=1); by default the overlap S^T S carries it                        // DG_TUNE=0 keeps the default splits

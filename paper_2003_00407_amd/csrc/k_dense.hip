@@ -60,6 +60,15 @@ __device__ __forceinline__ double2 gload2(const void* p) {
   const gd2 v = *(const __attribute__((address_space(1))) gd2*)(p);
   return double2{v.x, v.y};
 }
+typedef float gf2 __attribute__((ext_vector_type(2)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 gload2f(const void* p) {
+  const gf2 v = *(const __attribute__((address_space(1))) gf2*)(p);
+  return float2{v.x, v.y};
+}
+__device__ __forceinline__ void gstore2f(void* p, float x, float y) {
+  *(__attribute__((address_space(1))) gf2*)(p) = gf2{x, y};
+}
 __device__ __forceinline__ void gstore2(void* p, double x, double y) {
   *(__attribute__((address_space(1))) gd2*)(p) = gd2{x, y};
 }
@@ -102,6 +111,7 @@ constexpr int GP_R = 16;        // grid rows staged per step
 constexpr int GP_MAXCOL = 384;  // staged columns per workgroup (tiles are chosen to fit)
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64 lane layout (checked on the device): lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; result register q of lane l is D[l/16 + 4q][l%16].
@@ -355,6 +365,155 @@ __global__ void __launch_bounds__(GP_THREADS, MAXB <= 6 ? 4 : 2) k_gram(GramArgs
 }
 
 // ---------------------------------------------------------------------------
+// Gram of FP32 blocks on FP32 matrix cores (the FP32 parts of the mixed path).
+// Same tiles, work items, pair mode and partial sums as k_gram.  A workgroup stages
+// 32-row panels of FP32 values column-major in LDS (pitch 36 floats: the sixteen
+// columns of a fragment start on distinct 4-bank groups, so the 16-byte fragment
+// reads are conflict-free); per panel and output block the eight k-steps of
+// v_mfma_f32_16x16x4f32 are summed in FP32 and the panel's sum is added to FP64
+// accumulators, so rounding grows with the 32 products of a panel, not with N.
+// v_mfma_f32_16x16x4f32 (checked on the device): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; result register q of lane l is D[4 (l/16) + q][l%16].
+// ---------------------------------------------------------------------------
+constexpr int G3_R = 32;            // grid rows staged per step
+constexpr int G3_RP = G3_R + 4;     // floats per staged column
+constexpr int G3_MAXCOL = 384;
+
+__device__ __forceinline__ f4v mfma32_16x16x4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// PF: staged values per thread and step (16 columns per pass of the workgroup)
+template <int MAXB, int PF>
+__global__ void __launch_bounds__(GP_THREADS, 4) k_gram32(GramArgs A) {
+  const GramItem item = gram_item(A);
+  if (!item.valid) return;
+  const int e = item.e;
+  const ElemDev& E = A.elems[e];
+  if (A.active && !A.active[e]) return;
+  const int kS = kcode(A.kS, E);
+  const int kT = kcode(A.kT, E);
+  const int ni = A.S.nb * kS, nj = A.T.nb * kT;
+  const int bi = (ni + 15) >> 4, bj = (nj + 15) >> 4;
+  if (item.tile >= gram_ntiles(bi, bj, A.tb, A.sym)) return;
+  const GramTile g = gram_tile(item.tile, bi, bj, A.tb, A.sym, A.same, A.pair);
+  const int nblk_all = A.pair ? 2 * g.nloc : g.nloc;
+  const int split = item.split;
+  const int nrows = nrows_of(E, A.rows_e);
+  const int rows_per = ((nrows + A.nsplit - 1) / A.nsplit + G3_R - 1) / G3_R * G3_R;
+  const int r0 = split * rows_per;
+  const int r1 = min(nrows, r0 + rows_per);
+  const int nc = g.ncA + g.ncB + g.ncC;
+  const int offB = (A.same && g.diag) ? 0 : g.ncA;
+  const int offC = g.diag ? 0 : g.ncA + g.ncB;
+  extern __shared__ double gsm[];
+  float* sm = reinterpret_cast<float*>(gsm);                              // [nc][G3_RP]
+  const float** cp = reinterpret_cast<const float**>(sm + (size_t)nc * G3_RP);   // [nc]
+  for (int c = threadIdx.x; c < nc; c += GP_THREADS) {
+    const float* ptr = nullptr;
+    if (c < g.ncA) {
+      const int v = 16 * g.P0 + c;
+      if (v < ni) ptr = vcol<float>(E, A.S, v, kS);
+    } else if (c < g.ncA + g.ncB) {
+      const int v = 16 * g.Q0 + c - g.ncA;
+      if (A.same) {
+        if (v < ni) ptr = vcol<float>(E, A.S, v, kS);
+      } else if (v < nj) {
+        ptr = vcol<float>(E, A.T, v, kT);
+      }
+    } else {
+      const int v = 16 * g.Q0 + c - g.ncA - g.ncB;
+      if (v < ni) ptr = vcol<float>(E, A.S, v, kS);
+    }
+    cp[c] = ptr;
+  }
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cs = (nblk_all + 7) >> 3;
+  int bp[MAXB], bq[MAXB], bo[MAXB];
+  bool bv[MAXB];
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t) {
+    const int b = w * cs + t;
+    bv[t] = t < cs && b < nblk_all;
+    bp[t] = bq[t] = bo[t] = 0;
+    if (bv[t]) gram_run_block(g, b, A.pair, offB, offC, bp[t], bq[t], bo[t]);
+  }
+  const int l16 = lane & 15;
+  const int lrow = (lane >> 4) * (G3_R / 4);
+  d4v acc[MAXB];
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  constexpr int kCPP = GP_THREADS / G3_R;   // columns per pass of the workgroup
+  const int srow = threadIdx.x & (G3_R - 1), scol = threadIdx.x / G3_R;
+  float pre[PF];
+  auto load = [&](int rbase) {
+    const int rr = rbase + srow;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int c = scol + kCPP * u;
+      float v = 0.f;
+      if (c < nc) {
+        const float* ptr = cp[c];
+        if (ptr && rr < r1) v = gload<float>(ptr + rr);
+      }
+      pre[u] = v;
+    }
+  };
+  constexpr int KF = G3_R / 4;   // k-steps per panel = values per lane and fragment
+  auto frag = [&](int col, float (&f)[KF]) {
+    const float4* q = reinterpret_cast<const float4*>(sm + (size_t)(col + l16) * G3_RP + lrow);
+#pragma unroll
+    for (int m = 0; m < KF / 4; ++m) {
+      const float4 x = q[m];
+      f[4 * m] = x.x;
+      f[4 * m + 1] = x.y;
+      f[4 * m + 2] = x.z;
+      f[4 * m + 3] = x.w;
+    }
+  };
+  if (r0 < r1) load(r0);
+  for (int r = r0; r < r1; r += G3_R) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int c = scol + kCPP * u;
+      if (c < nc) sm[(size_t)c * G3_RP + srow] = pre[u];
+    }
+    __syncthreads();
+    if (r + G3_R < r1) load(r + G3_R);
+    float fa[KF];
+#pragma unroll
+    for (int j = 0; j < KF; ++j) fa[j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+      if (!bv[t]) continue;
+      if (t == 0 || bp[t] != bp[t - 1]) frag(bp[t], fa);   // uniform branch: bp is wave-uniform
+      float fb[KF];
+      frag(bq[t], fb);
+      f4v s = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < KF; ++j) s = mfma32_16x16x4(fa[j], fb[j], s);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[t][q] += (double)s[q];
+    }
+  }
+  double* out = A.part + (size_t)e * A.part_stride + (size_t)split * A.part_ld * A.part_ld;
+#pragma unroll
+  for (int t = 0; t < MAXB; ++t) {
+    if (!bv[t]) continue;
+    const bool second = bo[t] & 1;
+    double* o = second ? out + A.part_pair : out;
+    const int i0 = (bo[t] >> 16) * 16, j = ((bo[t] >> 1) & 0x7FFF) * 16 + l16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + 4 * (lane >> 4) + q;
+      if (i < ni && j < (second ? ni : nj)) o[(size_t)i * A.part_ld + j] = acc[t][q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Gram of FP32 blocks with BF16 matrix cores (the FP32 stage of the mixed path):
 // every FP32 value is split into three BF16 pieces x = x0 + x1 + x2 (24 significant
 // bits), the six products x_a y_b with a + b <= 2 of a 32-row stage are summed by
@@ -365,7 +524,6 @@ __global__ void __launch_bounds__(GP_THREADS, MAXB <= 6 ? 4 : 2) k_gram(GramArgs
 // B[k][l%16] for eight k that A and B share; result register q is D[4(l/16)+q][l%16].
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int GB_R = 32;          // rows per stage (the MFMA's k)
 constexpr int GB_PITCH = 40;      // BF16 per staged column (32 rows + pad)
@@ -1425,6 +1583,156 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 3 : 2) k_rotate(RotArgs
 }
 
 // ---------------------------------------------------------------------------
+// The same rotation for FP32 blocks on FP32 matrix cores (v_mfma_f32_16x16x4f32,
+// FP32 sums): C chunks of 32 rows staged transposed as FP32 (pitch 36 floats, the
+// eight coefficients of a lane two 16-byte reads), each lane's two row tiles are
+// adjacent rows, so S loads and output stores move 8 bytes per column.  Lane l's
+// result q of column tile t is output column 16 t + 4 (l / 16) + q.
+// ---------------------------------------------------------------------------
+constexpr int R3_CP = RT_CC + 4;
+
+template <int NCT>
+__global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 4 : 2) k_rotate32(RotArgs A) {
+  const int e = blockIdx.y;
+  const ElemDev& E = A.elems[e];
+  if (A.active && !A.active[e]) return;
+  const int kS = kcode(A.kS, E);
+  const int ncol = kcode(A.ncol, E);
+  const int cld = A.c_ld > 0 ? A.c_ld : ncol;
+  const int nrows = nrows_of(E, A.rows_e);
+  const int r0 = blockIdx.x * RT_ROWS;
+  if (r0 >= nrows) return;
+  int c0[2], c1[2];
+  for (int o = 0; o < 2; ++o) {
+    c0[o] = A.c_blockrows > 0 ? A.c0[o] * kS : A.c0[o];
+    c1[o] = A.c_blockrows > 0 ? A.c1[o] * kS : A.c1[o];
+  }
+  __shared__ __attribute__((aligned(16))) float sc[NCT * 16][R3_CP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kl = lane >> 4;
+  const int rr0 = r0 + w * RT_RT * 16 + 2 * (lane & 15);
+  const bool in0 = rr0 < nrows, in1 = rr0 + 1 < nrows;
+  const int nct = (ncol + 15) / 16;
+  const double* Cm = E.small + soff(A.c_off, E);
+  f4v acc[RT_RT][NCT];
+#pragma unroll
+  for (int u = 0; u < RT_RT; ++u)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[u][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int nseg = A.nout > 1 ? 2 : 1;
+  for (int sg = 0; sg < nseg; ++sg) {
+    int lo, hi;
+    if (A.nout > 1) {
+      lo = sg == 0 ? c0[1] : c0[0];
+      hi = sg == 0 ? c1[1] : c0[1];
+    } else {
+      lo = c0[0];
+      hi = c1[0];
+    }
+    const float* sb0 = reinterpret_cast<const float*>(E.blk[A.S.blk[0]]);
+    const long long d1 = A.S.nb > 1 ? reinterpret_cast<const float*>(E.blk[A.S.blk[1]]) - sb0 : 0;
+    const long long d2 = A.S.nb > 2 ? reinterpret_cast<const float*>(E.blk[A.S.blk[2]]) - sb0 : 0;
+    const long long ldS = E.ld;
+    auto scol = [&](int c) -> const float* {
+      const bool b1 = c >= kS, b2 = c >= 2 * kS;
+      const long long off = (b2 ? d2 : (b1 ? d1 : 0LL)) + (long long)(c - (b2 ? 2 * kS : (b1 ? kS : 0))) * ldS;
+      return sb0 + off;
+    };
+    float av[RT_CC / 4][RT_RT], an[RT_CC / 4][RT_RT];
+    // branch-free, as in k_rotate: one 8-byte pair from a valid address per column
+    auto load_s = [&](int cb, float (&dst)[RT_CC / 4][RT_RT]) {
+#pragma unroll
+      for (int ks = 0; ks < RT_CC / 4; ++ks) {
+        const int c = cb + kl * (RT_CC / 4) + ks;
+        const bool cin = c < hi;
+        const float* col = scol(cin ? c : lo);
+        const float2 v = gload2f(col + (in0 ? rr0 : 0));
+        dst[ks][0] = (cin && in0) ? v.x : 0.f;
+        dst[ks][1] = (cin && in1) ? v.y : 0.f;
+      }
+    };
+    constexpr int CPT = (RT_CC * NCT * 16 + RT_THREADS - 1) / RT_THREADS;
+    double cn[CPT];
+    auto load_c = [&](int cb) {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int idx = threadIdx.x + u * RT_THREADS;
+        const int cc = idx / (NCT * 16), j = idx % (NCT * 16);
+        const int c = cb + cc;
+        const bool ok = idx < RT_CC * NCT * 16 && c < hi && j < ncol;
+        const double v = gload<double>(Cm + (ok ? (size_t)c * cld + j : 0));
+        cn[u] = ok ? v : 0.0;
+      }
+    };
+    if (lo < hi) {
+      load_s(lo, an);
+      load_c(lo);
+    }
+    for (int cb = lo; cb < hi; cb += RT_CC) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int idx = threadIdx.x + u * RT_THREADS;
+        if (idx < RT_CC * NCT * 16) sc[idx % (NCT * 16)][idx / (NCT * 16)] = (float)cn[u];
+      }
+#pragma unroll
+      for (int ks = 0; ks < RT_CC / 4; ++ks)
+#pragma unroll
+        for (int u = 0; u < RT_RT; ++u) av[ks][u] = an[ks][u];
+      __syncthreads();
+      if (cb + RT_CC < hi) {
+        load_s(cb + RT_CC, an);
+        load_c(cb + RT_CC);
+      }
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        if (t >= nct) continue;
+        const float4* q = reinterpret_cast<const float4*>(&sc[t * 16 + (lane & 15)][kl * (RT_CC / 4)]);
+        float cf[RT_CC / 4];
+#pragma unroll
+        for (int m = 0; m < RT_CC / 16; ++m) {
+          const float4 v = q[m];
+          cf[4 * m] = v.x;
+          cf[4 * m + 1] = v.y;
+          cf[4 * m + 2] = v.z;
+          cf[4 * m + 3] = v.w;
+        }
+#pragma unroll
+        for (int ks = 0; ks < RT_CC / 4; ++ks)
+#pragma unroll
+          for (int u = 0; u < RT_RT; ++u) acc[u][t] = mfma32_16x16x4(cf[ks], av[ks][u], acc[u][t]);
+      }
+    }
+    // store the output this segment completes: lane holds out[rows rr0, rr0 + 1][col 16 t + 4 kl + q]
+    const int o = (A.nout > 1 && sg == 0) ? 1 : 0;
+    float* out = reinterpret_cast<float*>(E.blk[A.out_blk[o]]);
+    const double beta = A.beta[o];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      if (t >= nct) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = t * 16 + 4 * kl + q;
+        if (j >= ncol) continue;
+        float* p = out + (size_t)j * E.ld + rr0;
+        if (in1) {
+          double v0 = A.alpha * (double)acc[0][t][q], v1 = A.alpha * (double)acc[1][t][q];
+          if (beta != 0.0) {
+            const float2 prev = gload2f(p);
+            v0 += beta * (double)prev.x;
+            v1 += beta * (double)prev.y;
+          }
+          gstore2f(p, (float)v0, (float)v1);
+        } else if (in0) {
+          const double prev = beta != 0.0 ? beta * (double)*p : 0.0;
+          *p = (float)(prev + A.alpha * (double)acc[0][t][q]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The same rotation for FP32 blocks on BF16 matrix cores (the FP32 stage of the
 // mixed path): S values and C coefficients are split into three BF16 pieces each
 // (24 significant bits), and the six products s_a c_b with a + b <= 2 of every
@@ -1915,10 +2223,23 @@ static void gram_attrs() {
     set_lds_limit((const void*)k_gram_bf16<MB, 8>, 96000);
     set_lds_limit((const void*)k_gram_bf16<MB, 18>, 96000);
   }
+  if constexpr (MB <= 6) {
+    set_lds_limit((const void*)k_gram32<MB, 8>, GP_LDS_LIMIT);
+    set_lds_limit((const void*)k_gram32<MB, 16>, GP_LDS_LIMIT);
+    set_lds_limit((const void*)k_gram32<MB, 24>, GP_LDS_LIMIT);
+  }
 }
 
 template <int MB>
-static void launch_gram_mb(int prec, int pf, dim3 g, size_t lds, hipStream_t s, const GramArgs& ga) {
+static void launch_gram_mb(int prec, int pf, dim3 g, size_t lds, hipStream_t s, const GramArgs& ga, bool bf16) {
+  if (prec != DG_FP64 && !bf16) {
+    if constexpr (MB <= 6) {
+      if (pf <= 8) hipLaunchKernelGGL((k_gram32<MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
+      else if (pf <= 16) hipLaunchKernelGGL((k_gram32<MB, 16>), g, dim3(GP_THREADS), lds, s, ga);
+      else hipLaunchKernelGGL((k_gram32<MB, 24>), g, dim3(GP_THREADS), lds, s, ga);
+    }
+    return;
+  }
   if (prec == DG_FP64) {
     if (pf <= 8) hipLaunchKernelGGL((k_gram<double, MB, 8>), g, dim3(GP_THREADS), lds, s, ga);
     else if (pf <= 16) hipLaunchKernelGGL((k_gram<double, MB, 16>), g, dim3(GP_THREADS), lds, s, ga);
@@ -2014,8 +2335,11 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
   }
   const int bj_max = (maxnj + 15) / 16;
   // FP64: up to 12 blocks per wave (16 spill registers) and 384 staged columns; BF16x3: 8 and 288
-  const int cap_blocks = prec == DG_FP64 ? 6 : 6;
-  const int cap_cols = prec == DG_FP64 ? GP_MAXCOL : 128;
+  // FP64 and FP32 (FP32 matrix cores): at most 6 blocks per wave and 384 staged columns;
+  // BF16x3 (DG_BF16=1): 6 blocks and 128 columns
+  const bool bf16 = prec != DG_FP64 && c.bf16;
+  const int cap_blocks = 6;
+  const int cap_cols = prec == DG_FP64 ? GP_MAXCOL : (bf16 ? 128 : G3_MAXCOL);
   const GramPlan pl = plan_gram_tiles(bis, bj_max, sym, same ? 1 : 0, pair ? 1 : 0, cap_blocks, cap_cols);
   if (pl.maxblk == 0) {
     set_error("Gram: no tile fits the per-workgroup limits");
@@ -2028,7 +2352,7 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
       maxb = m;
       break;
     }
-  // staged values per thread: FP64 GP_THREADS / GP_R columns per pass; BF16: 16 per pass
+  // staged values per thread: FP64 GP_THREADS / GP_R columns per pass; FP32 and BF16: 16 per pass
   const int pf = prec == DG_FP64 ? (pl.maxnc + GP_THREADS / GP_R - 1) / (GP_THREADS / GP_R) : (pl.maxnc + 15) / 16;
   const int groups = pl.ntiles;
   // row-range split: row ranges of about 8192 rows of the largest element, and at least
@@ -2057,7 +2381,8 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     flops += (sym ? r * ni * (ni + 1.0) : 2.0 * r * ni * nj) * (pair ? 2.0 : 1.0);
   }
   const size_t lds = prec == DG_FP64 ? (size_t)GP_RP * pl.maxnc * sizeof(double) + (size_t)pl.maxnc * sizeof(void*)
-                                     : (size_t)3 * pl.maxnc * GB_PITCH * 2 + (size_t)pl.maxnc * sizeof(void*);
+                     : !bf16       ? (size_t)G3_RP * pl.maxnc * sizeof(float) + (size_t)pl.maxnc * sizeof(void*)
+                                   : (size_t)3 * pl.maxnc * GB_PITCH * 2 + (size_t)pl.maxnc * sizeof(void*);
   auto launch = [&](int ns) -> int {
     ga.nsplit = ns;
     ga.part_pair = ns * part_sq;
@@ -2065,13 +2390,13 @@ static int gram_impl(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T,
     const long long n_rr8 = ((long long)ns * c.n_elem + 7) / 8 * 8;
     dim3 g1((unsigned)(groups * n_rr8));
     switch (maxb) {
-      case 1: launch_gram_mb<1>(prec, pf, g1, lds, c.stream, ga); break;
-      case 2: launch_gram_mb<2>(prec, pf, g1, lds, c.stream, ga); break;
-      case 3: launch_gram_mb<3>(prec, pf, g1, lds, c.stream, ga); break;
-      case 4: launch_gram_mb<4>(prec, pf, g1, lds, c.stream, ga); break;
-      case 6: launch_gram_mb<6>(prec, pf, g1, lds, c.stream, ga); break;
-      case 8: launch_gram_mb<8>(prec, pf, g1, lds, c.stream, ga); break;
-      case 12: launch_gram_mb<12>(prec, pf, g1, lds, c.stream, ga); break;
+      case 1: launch_gram_mb<1>(prec, pf, g1, lds, c.stream, ga, bf16); break;
+      case 2: launch_gram_mb<2>(prec, pf, g1, lds, c.stream, ga, bf16); break;
+      case 3: launch_gram_mb<3>(prec, pf, g1, lds, c.stream, ga, bf16); break;
+      case 4: launch_gram_mb<4>(prec, pf, g1, lds, c.stream, ga, bf16); break;
+      case 6: launch_gram_mb<6>(prec, pf, g1, lds, c.stream, ga, bf16); break;
+      case 8: launch_gram_mb<8>(prec, pf, g1, lds, c.stream, ga, bf16); break;
+      case 12: launch_gram_mb<12>(prec, pf, g1, lds, c.stream, ga, bf16); break;
       default:
         set_error("Gram: unsupported block count");
         return DG_ERR_SHAPE;
@@ -2212,12 +2537,17 @@ int launch_rotate(Ctx& c, int prec, const RotArgs& a_in) {
     }
   }
   TimedScope ts(c, TC_ROT, flops);
-  // output column tiles: 3 (up to 48 columns) or 6 (up to 96); FP32 blocks on BF16 matrix cores
-  if (k <= 48) {
-    if (prec == DG_FP64) hipLaunchKernelGGL((k_rotate<double, 3>), g, dim3(RT_THREADS), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_rotate_bf16<3>), g, dim3(RT_THREADS), 0, c.stream, a);
+  // output column tiles: 3 (up to 48 columns) or 6 (up to 96); FP32 blocks on FP32 matrix
+  // cores (BF16 matrix cores with DG_BF16=1)
+  const bool k3 = k <= 48;
+  if (prec == DG_FP64) {
+    if (k3) hipLaunchKernelGGL((k_rotate<double, 3>), g, dim3(RT_THREADS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rotate<double, 6>), g, dim3(RT_THREADS), 0, c.stream, a);
+  } else if (!c.bf16) {
+    if (k3) hipLaunchKernelGGL((k_rotate32<3>), g, dim3(RT_THREADS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rotate32<6>), g, dim3(RT_THREADS), 0, c.stream, a);
   } else {
-    if (prec == DG_FP64) hipLaunchKernelGGL((k_rotate<double, 6>), g, dim3(RT_THREADS), 0, c.stream, a);
+    if (k3) hipLaunchKernelGGL((k_rotate_bf16<3>), g, dim3(RT_THREADS), 0, c.stream, a);
     else hipLaunchKernelGGL((k_rotate_bf16<6>), g, dim3(RT_THREADS), 0, c.stream, a);
   }
   DG_HIP(hipGetLastError());

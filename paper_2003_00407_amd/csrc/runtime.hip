@@ -386,6 +386,7 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   if (const char* ow = std::getenv("DG_ORTH_W")) c->orth_w = std::atoi(ow) != 0;
   if (const char* fh = std::getenv("DG_FRESH_HP")) c->fresh_hp_all = std::atoi(fh) != 0;
   if (const char* ht = std::getenv("DG_HP_TOL")) c->hp_tol_env = std::atof(ht);
+  if (const char* bf = std::getenv("DG_BF16")) c->bf16 = std::atoi(bf) != 0;
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {

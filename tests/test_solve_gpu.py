@@ -80,8 +80,11 @@ def test_slab_lobpcg_vs_oracle_and_alb():
             assert np.max(np.abs(sv[offe[k]:offe[k + 1]] - s_ref)) < 1e-7
 
 
-def test_slab_mixed_precision_vs_oracle():
-    """FP32 H*psi + FP32 subspace GEMMs, FP64 small dense, then FP64 refinement."""
+@pytest.mark.parametrize("bf16", [0, 1])
+def test_slab_mixed_precision_vs_oracle(bf16, monkeypatch):
+    """FP32 H*psi + FP32 subspace GEMMs (FP32 matrix cores; BF16x3 with DG_BF16=1),
+    FP64 small dense, then FP64 refinement."""
+    monkeypatch.setenv("DG_BF16", str(bf16))
     els = W.small_slab(n_states=8)[:4]
     E, eig, res, iters, st = _solve(els, precision=1, seed_base=300)
     assert st == 0
