@@ -247,6 +247,8 @@ struct Ctx {
   int gram_max_split = 16;
   std::map<long long, int> gram_split_table;   // autotuned row splits per Gram shape
   bool autotune = true;
+  bool mixed_refine = false;                   // DG_MIXED_REFINE=1: refinement with FP32 search blocks after
+                                               // the FP32 stage (default: FP64 LOBPCG refinement)
   bool bf16 = false;                           // DG_BF16=1: FP32 blocks' Grams and rotations as BF16x3
   bool fresh_hp_all = false;                   // DG_FRESH_HP=1: HP = H P for every element each LOBPCG step
   bool orth_w = false;                         // W <- W - X (X^T W) before the projected problem
@@ -258,6 +260,7 @@ struct Ctx {
   double rr_pivot_tol = 1e-13;     // overlap-Cholesky breakdown threshold (FP64 data)
   double rr_drop_tol = 1e-8;       // W/P columns with smaller scaled overlap pivots leave the basis
   double rr_drop_env = -1.0;       // DG_RR_DROP override (diagnostics)
+  double rr_drop_refine_env = -1.0;  // DG_RR_DROP_REFINE: the mixed refinement's drop threshold
   double hp_tol = 1e-6;            // scaled overlap pivots below this: H P applied afresh, not rotated
   double hp_tol_env = -1.0;        // DG_HP_TOL override
   double rr_ortol = 1e-5;          // cluster tolerance of the inverse iteration (relative to ||T||)
@@ -293,7 +296,12 @@ bool grid_supported(int nx, int ny, int nz);
 int launch_hpsi(Ctx& c, int elem, int ncols, int prec, int in_blk, int out_blk, const int* active);
 // H*psi on caller buffers (ext.x -> ext.y), projector overlaps in ext.nlc
 int launch_hpsi_ext(Ctx& c, int elem, int ncols, int prec, const ExtBufs& ext);
-int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active);
+int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active,
+                 bool r_given = false);
+// mixed refinement: R = HX - X theta and X in FP32 (FP64 X, HX in), and the projected
+// matrices of [X W P] from the FP32 Grams of [W P X32] with [HW HP R]
+int launch_mixed_split(Ctx& c, int x_blk, int hx_blk, int r_blk, int x32_blk, const int* active);
+int launch_mixed_fix(Ctx& c, int nb, const int* active);
 
 // ---- dense launchers (k_dense.hip) ----
 struct ColSet {
@@ -316,6 +324,8 @@ struct RotArgs {
   int ncol;            // output columns (<= 0: E.K)
   int c_blockrows;     // if > 0: c0/c1 are in units of S blocks (multiplied by kS)
   int rows_e;          // 1: the first |E_k| rows only
+  int add32;           // FP64 rotation, 1: the beta term reads FP32 block add32_blk[o], not the output
+  int add32_blk[2];
 };
 int launch_gram(Ctx& c, int prec, const ColSet& S, int kS, const ColSet& T, int kT,
                 long long out_off, const int* active, int sym);

@@ -1565,16 +1565,25 @@ __global__ void __launch_bounds__(RT_THREADS, NCT <= 3 ? 3 : 2) k_rotate(RotArgs
         const int j = t * 16 + kl + 4 * q;
         if (j >= ncol) continue;
         T* p = out + (size_t)j * E.ld + rr0;
+        // the beta term: the output's own values, or those of an FP32 block
+        const float* p32 = A.add32 ? reinterpret_cast<const float*>(E.blk[A.add32_blk[o]]) + (size_t)j * E.ld + rr0
+                                   : nullptr;
         if (in1) {
           double2 v = {A.alpha * acc[0][t][q], A.alpha * acc[1][t][q]};
           if (beta != 0.0) {
-            const double2 prev = gload2(p);
+            double2 prev;
+            if (p32) {
+              const float2 f = gload2f(p32);
+              prev = double2{(double)f.x, (double)f.y};
+            } else {
+              prev = gload2(p);
+            }
             v.x += beta * prev.x;
             v.y += beta * prev.y;
           }
           gstore2(p, v.x, v.y);
         } else if (in0) {
-          const double prev = beta != 0.0 ? beta * double(*p) : 0.0;
+          const double prev = beta != 0.0 ? beta * (p32 ? (double)*p32 : double(*p)) : 0.0;
           *p = T(prev + A.alpha * acc[0][t][q]);
         }
       }
@@ -2111,6 +2120,75 @@ __global__ void __launch_bounds__(256) k_convert(const ElemDev* elems, int src_b
   else reinterpret_cast<float*>(E.blk[dst_blk])[o] = float(v);
 }
 
+// Mixed refinement, per active element and column j < K: the residual
+// r_j = hx_j - theta_j x_j, formed in FP64 and stored in FP32 (its rounding is relative
+// to r, not to hx), and x_j rounded to FP32.
+__global__ void __launch_bounds__(256) k_mixed_split(const ElemDev* elems, const int* active, int x_blk,
+                                                     int hx_blk, int r_blk, int x32_blk) {
+  const int e = blockIdx.z;
+  const ElemDev& E = elems[e];
+  if (active && !active[e]) return;
+  const int j = blockIdx.y;
+  if (j >= E.K) return;
+  const int KP = E.kmax3 + 2;
+  const double th = E.small[SmallLayout::vec(KP) + VS_THETA * KP + j];
+  const double* X = reinterpret_cast<const double*>(E.blk[x_blk]) + (size_t)j * E.ld;
+  const double* HX = reinterpret_cast<const double*>(E.blk[hx_blk]) + (size_t)j * E.ld;
+  float* R = reinterpret_cast<float*>(E.blk[r_blk]) + (size_t)j * E.ld;
+  float* X32 = reinterpret_cast<float*>(E.blk[x32_blk]) + (size_t)j * E.ld;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = blockIdx.x * 1024 + u * 256 + threadIdx.x;
+    if (r >= E.N) break;
+    const double x = X[r];
+    R[r] = (float)(HX[r] - th * x);
+    X32[r] = (float)x;
+  }
+}
+
+// Mixed refinement: the projected matrices of [X W P] (G: overlap, A: H) from the FP32
+// Grams of S' = [W P X32] (Gs = S'^T S') and T' = [HW HP R] (As = S'^T T', upper blocks):
+//   G_XX = I and A_XX = Theta (X holds Ritz vectors),
+//   G_QX = Gs_QX and A_QX = Q^T R + G_QX Theta for Q = W, P,
+//   G_QQ', A_QQ' = Gs, As,
+// both symmetric.  A_QX - theta_j G_QX e_j = Q^T r_j holds whatever the rounding of
+// G_QX, so the FP32 Grams perturb the correction only in second order.
+__global__ void __launch_bounds__(256) k_mixed_fix(const ElemDev* elems, const int* active, int nb) {
+  const int e = blockIdx.x;
+  const ElemDev& E = elems[e];
+  if (active && !active[e]) return;
+  const int K = E.K, n = nb * K;
+  const int KP = E.kmax3 + 2;
+  const double* Gs = E.small + SmallLayout::V(KP);
+  const double* As = E.small + SmallLayout::U(KP);
+  double* G = E.small + SmallLayout::G(KP);
+  double* Am = E.small + SmallLayout::A(KP);
+  const double* th = E.small + SmallLayout::vec(KP) + VS_THETA * KP;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    const int bi = i / K, bj = j / K;
+    // [X W P] index -> [W P X] index
+    const int oi = (bi == 0 ? nb - 1 : bi - 1) * K + (i - bi * K);
+    const int oj = (bj == 0 ? nb - 1 : bj - 1) * K + (j - bj * K);
+    double g, a;
+    if (bi == 0 && bj == 0) {
+      g = i == j ? 1.0 : 0.0;
+      a = i == j ? th[i] : 0.0;
+    } else if (bi == 0 || bj == 0) {
+      // one index in X: read the (Q row, X column) entries, computed directly in As
+      const int q = bi == 0 ? oj : oi, x = bi == 0 ? oi : oj;
+      const int xi = bi == 0 ? i : j;
+      g = Gs[(size_t)q * n + x];
+      a = As[(size_t)q * n + x] + g * th[xi];
+    } else {
+      g = Gs[(size_t)oi * n + oj];
+      a = As[(size_t)oi * n + oj];
+    }
+    G[(size_t)i * n + j] = g;
+    Am[(size_t)i * n + j] = a;
+  }
+}
+
 // Seeded Gaussian start: value (row r, column j) of element g = e + elem_base is a
 // Box-Muller normal from two SplitMix64 outputs of the counter (seed, g, j, r), so
 // the block does not depend on how the batch is split into element groups.
@@ -2629,6 +2707,23 @@ int launch_random_block(Ctx& c, int prec, int blk, unsigned long long seed) {
     hipLaunchKernelGGL(k_random_block<double>, g, dim3(256), 0, c.stream, c.elems_dev, blk, seed, c.elem_base);
   else
     hipLaunchKernelGGL(k_random_block<float>, g, dim3(256), 0, c.stream, c.elems_dev, blk, seed, c.elem_base);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_mixed_split(Ctx& c, int x_blk, int hx_blk, int r_blk, int x32_blk, const int* active) {
+  int maxk, maxN, maxE;
+  max_dims(c, 0, &maxk, &maxN, &maxE);
+  dim3 g((maxN + 1023) / 1024, maxk, c.n_elem);
+  TimedScope ts(c, TC_OTHER);
+  hipLaunchKernelGGL(k_mixed_split, g, dim3(256), 0, c.stream, c.elems_dev, active, x_blk, hx_blk, r_blk, x32_blk);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_mixed_fix(Ctx& c, int nb, const int* active) {
+  TimedScope ts(c, TC_OTHER);
+  hipLaunchKernelGGL(k_mixed_fix, dim3(c.n_elem), dim3(256), 0, c.stream, c.elems_dev, active, nb);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

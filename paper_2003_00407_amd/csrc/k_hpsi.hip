@@ -59,6 +59,7 @@ struct PlaneArgs {
   const double* theta_base;  // TFWD: per-element theta at small + vec(VS_THETA)
   int k3;                 // small-layout K3 (for theta lookup)
   ExtBufs ext;            // caller buffers for block ids kExtX / kExtY
+  int r_given = 0;        // TFWD: aux already holds r = HX - X theta (in_blk is not read)
 };
 
 // Columns 2p and 2p+1 of a block (the second may be absent).
@@ -144,7 +145,13 @@ __global__ void __launch_bounds__(512) k_plane(PlaneArgs A) {
     const double* th = E.small + SmallLayout::vec(KP) + VS_THETA * KP;
     const T ta = T(th[2 * pair]);
     const T tb = xx.b ? T(th[2 * pair + 1]) : T(0);
-    if (zok) {
+    if (zok && A.r_given) {
+      for (int i = lt; i < NXY; i += TPP) {
+        T re = hx.a[zoff + i];
+        T im = hx.b ? hx.b[zoff + i] : T(0);
+        P[(i / NX) * PITCH + (i % NX)] = {re, im};
+      }
+    } else if (zok) {
       for (int i = lt; i < NXY; i += TPP) {
         T re = hx.a[zoff + i] - ta * xx.a[zoff + i];
         T im = xx.b ? (hx.b[zoff + i] - tb * xx.b[zoff + i]) : T(0);
@@ -696,9 +703,10 @@ int launch_hpsi_ext(Ctx& c, int elem, int ncols, int prec, const ExtBufs& ext) {
                          : hpsi_typed<float>(c, elem, ncols, kExtX, kExtY, nullptr, ext);
 }
 
-// W <- Teter(HX - X theta), three passes, for every element in place in W
+// W <- Teter(HX - X theta), three passes, for every element in place in W (r_given:
+// hx_blk already holds the residual)
 template <typename T>
-static int teter_typed(Ctx& c, int x_blk, int hx_blk, int w_blk, int k3, const int* active) {
+static int teter_typed(Ctx& c, int x_blk, int hx_blk, int w_blk, int k3, const int* active, bool r_given) {
   hipStream_t s = c.stream;
   double tw = 0.0;
   for (int e = 0; e < c.n_elem; ++e)
@@ -706,7 +714,8 @@ static int teter_typed(Ctx& c, int x_blk, int hx_blk, int w_blk, int k3, const i
   TimedScope ts(c, TC_TETER, tw);   // read X, HX, write W
   for (const ShapeClass& sc : c.classes) {
     const int npairs = (sc.max_k + 1) / 2;
-    PlaneArgs pa{c.elems_dev, sc.elem_list_dev, active, x_blk, w_blk, hx_blk, -1, nullptr, k3};
+    PlaneArgs pa{c.elems_dev, sc.elem_list_dev, active, r_given ? hx_blk : x_blk, w_blk, hx_blk, -1, nullptr, k3};
+    pa.r_given = r_given ? 1 : 0;
     if (!dispatch_plane<T, PM_TFWD>(sc.nx, pa, sc.nz, npairs, sc.nelem, s)) return DG_ERR_SHAPE;
     ZArgs za{c.elems_dev, sc.elem_list_dev, active, w_blk, w_blk, -1, k3};
     if (!dispatch_z<T, ZM_TETER>(sc.nz, za, sc.nx * sc.ny, npairs, sc.nelem, s)) return DG_ERR_SHAPE;
@@ -717,9 +726,9 @@ static int teter_typed(Ctx& c, int x_blk, int hx_blk, int w_blk, int k3, const i
   return DG_OK;
 }
 
-int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active) {
-  return prec == DG_FP64 ? teter_typed<double>(c, x_blk, hx_blk, w_blk, k3, active)
-                         : teter_typed<float>(c, x_blk, hx_blk, w_blk, k3, active);
+int launch_teter(Ctx& c, int prec, int x_blk, int hx_blk, int w_blk, int k3, const int* active, bool r_given) {
+  return prec == DG_FP64 ? teter_typed<double>(c, x_blk, hx_blk, w_blk, k3, active, r_given)
+                         : teter_typed<float>(c, x_blk, hx_blk, w_blk, k3, active, r_given);
 }
 
 // d/dx, d/dy, d/dz of the first J_k columns of block in_blk into out blocks (FP64,

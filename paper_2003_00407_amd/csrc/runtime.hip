@@ -382,11 +382,13 @@ int create(Ctx** out, int n_elem, const dg_element_desc* d, const dg_options* op
   if (const char* lv = std::getenv("DG_LOG")) c->log_level = std::atoi(lv);
   if (const char* ot = std::getenv("DG_RR_ORTOL")) c->rr_ortol = std::atof(ot);
   if (const char* dt = std::getenv("DG_RR_DROP")) c->rr_drop_env = std::atof(dt);
+  if (const char* dr = std::getenv("DG_RR_DROP_REFINE")) c->rr_drop_refine_env = std::atof(dr);
   if (const char* tu = std::getenv("DG_TUNE")) c->autotune = std::atoi(tu) != 0;
   if (const char* ow = std::getenv("DG_ORTH_W")) c->orth_w = std::atoi(ow) != 0;
   if (const char* fh = std::getenv("DG_FRESH_HP")) c->fresh_hp_all = std::atoi(fh) != 0;
   if (const char* ht = std::getenv("DG_HP_TOL")) c->hp_tol_env = std::atof(ht);
   if (const char* bf = std::getenv("DG_BF16")) c->bf16 = std::atoi(bf) != 0;
+  if (const char* mr = std::getenv("DG_MIXED_REFINE")) c->mixed_refine = std::atoi(mr) != 0;
   char* A = c->arena;
   hipStream_t s = c->stream;
   auto cpy = [&](size_t off, const void* src, size_t bytes) -> int {

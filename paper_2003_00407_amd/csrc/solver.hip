@@ -362,6 +362,169 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
   return DG_OK;
 }
 
+// Mixed refinement after the FP32 stage (LOBPCG).  X and HX stay FP64; the search
+// blocks W, P and their images HW, HP are FP32 (FP32 H*psi and preconditioner, Grams
+// and rotations on FP32 matrix cores).  The projected problem takes the FP64
+// residual R = HX - X Theta, rounded to FP32, in place of HX (k_mixed_fix), so FP32
+// rounding perturbs each correction only relative to its own size; X' = X C_X + P'
+// is an FP64 rotation plus the FP32 P', and HX' = H X' is applied in FP64.  At the
+// end an FP64 Rayleigh-Ritz step on span(X) restores an orthonormal FP64 Ritz basis;
+// elements whose residual is then above tol continue.
+static int run_mixed_refine(Ctx& c, double tol, int max_iter, int* iters, int* n_done) {
+  int st;
+  int* active = c.dev_active;
+  auto activate_all = [&]() -> int {
+    std::vector<int> ones(c.n_elem, 1);
+    c.host_ints = ones;
+    DG_HIP(hipMemcpyAsync(active, c.host_ints.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice, c.stream));
+    c.active_host.assign(c.n_elem, 1);
+    return DG_OK;
+  };
+  if ((st = activate_all())) return st;
+  {
+    std::vector<int> zeros(c.n_elem, 0);
+    c.host_ints2 = zeros;
+    DG_HIP(hipMemcpyAsync(c.dev_iters, c.host_ints2.data(), sizeof(int) * c.n_elem, hipMemcpyHostToDevice,
+                          c.stream));
+  }
+  // X columns have an exact unit overlap here.  W/P columns carry FP32 Gram rounding,
+  // which shifts the Rayleigh quotient of a direction with scaled pivot p by about
+  // eps_32 ||H|| / p: below p = 1e-3 such a direction can pose as a wanted eigenpair
+  // (measured on C4: 1e-5 and 1e-4 let single elements diverge), so it leaves the basis
+  c.rr_pivot_tol = 1e-13;
+  c.rr_drop_tol = c.rr_drop_refine_env >= 0.0 ? c.rr_drop_refine_env : 1e-3;
+  c.hp_tol = c.hp_tol_env >= 0.0 ? c.hp_tol_env : 1e-3;
+  if ((st = reset_breakdowns(c))) return st;
+  // start: H X in FP64, Rayleigh-Ritz on span(X); the carried FP32 P (in T1) becomes P
+  if ((st = launch_hpsi(c, -1, 0, DG_FP64, B_X, B_HX, active))) return st;
+  if ((st = rr_and_rotate(c, DG_FP64, 1, active, false))) return st;
+  if ((st = launch_hpsi(c, -1, 0, DG_FP32, B_P, B_HP, active))) return st;
+  bool have_p = true;
+  auto step = [&](int nb) -> int {
+    int s2;
+    // R = HX - X Theta (into T0) and X (into T1), FP32
+    if ((s2 = launch_mixed_split(c, B_X, B_HX, B_T0, B_T1, active))) return s2;
+    // W = T(R), H W
+    if ((s2 = launch_teter(c, DG_FP32, B_T0, B_T0, B_W, 0, active, true))) return s2;
+    if ((s2 = launch_hpsi(c, -1, 0, DG_FP32, B_W, B_HW, active))) return s2;
+    // FP32 Grams of S' = [W P X] with [S' | T'], T' = [HW HP R], then the projected matrices
+    ColSet S = nb == 3 ? ColSet{3, {B_W, B_P, B_T1}} : ColSet{2, {B_W, B_T1, 0}};
+    ColSet T = nb == 3 ? ColSet{3, {B_HW, B_HP, B_T0}} : ColSet{2, {B_HW, B_T0, 0}};
+    if ((s2 = launch_gram_pair(c, DG_FP32, S, KC_K, T, KC_K, small_code(2), small_code(3), active))) return s2;
+    if ((s2 = launch_mixed_fix(c, nb, active))) return s2;
+    if ((s2 = launch_rr(c, nb, 0, 0, RR_GEN, active))) return s2;
+    // P' = [W P] C_WP into T1, HP' = [HW HP] C_WP into T0 (FP32)
+    RotArgs ra{};
+    ra.active = active;
+    ra.kS = KC_K;
+    ra.nout = 1;
+    ra.c0[0] = 1;
+    ra.c1[0] = nb;
+    ra.alpha = 1.0;
+    ra.c_off = small_code(4);
+    ra.ncol = KC_K;
+    ra.c_blockrows = 1;
+    ra.S = ColSet{nb, {B_X, B_W, B_P}};
+    ra.out_blk[0] = B_T1;
+    if ((s2 = launch_rotate(c, DG_FP32, ra))) return s2;
+    ra.S = ColSet{nb, {B_HX, B_HW, B_HP}};
+    ra.out_blk[0] = B_T0;
+    if ((s2 = launch_rotate(c, DG_FP32, ra))) return s2;
+    // H P' afresh (FP32) where the basis was nearly dependent
+    {
+      const int* mask = (c.fresh_hp_all || !c.dev_hpflag) ? active : c.dev_hpflag;
+      std::vector<int> saved;
+      const bool account = mask == c.dev_hpflag && c.timing && !c.capturing;
+      if (account) {
+        std::vector<int> fl(c.n_elem);
+        if ((s2 = sync_read(c, fl.data(), c.dev_hpflag, sizeof(int) * c.n_elem))) return s2;
+        saved = c.active_host;
+        c.active_host = fl;
+      }
+      s2 = launch_hpsi(c, -1, 0, DG_FP32, B_T1, B_T0, mask);
+      if (account) c.active_host = saved;
+      if (s2) return s2;
+    }
+    // X' = X C_X + P' into W (FP64)
+    RotArgs rx{};
+    rx.active = active;
+    rx.kS = KC_K;
+    rx.nout = 1;
+    rx.c0[0] = 0;
+    rx.c1[0] = 1;
+    rx.beta[0] = 1.0;
+    rx.alpha = 1.0;
+    rx.c_off = small_code(4);
+    rx.ncol = KC_K;
+    rx.c_blockrows = 1;
+    rx.add32 = 1;
+    rx.S = ColSet{1, {B_X, 0, 0}};
+    rx.out_blk[0] = B_W;
+    rx.add32_blk[0] = B_T1;
+    if ((s2 = launch_rotate(c, DG_FP64, rx))) return s2;
+    // HX' = H X' applied afresh in FP64, so HX stays exact and FP32 rounding stays in
+    // the search blocks (measured on C4: a rotated HX' = HX C_X + HP' gathers the FP32
+    // rounding of HP' step after step and stalls hard elements near 5e-8, and even with
+    // a refresh whenever the residual fell tenfold single elements diverged)
+    if ((s2 = launch_hpsi(c, -1, 0, DG_FP64, B_W, B_HW, active))) return s2;
+    // new X = W, HX = HW, P = T1, HP = T0; the other blocks are free
+    int perm[kMaxBlocks] = {B_W, B_P, B_T1, B_HW, B_HP, B_T0, B_X, B_HX};
+    return launch_permute(c, perm, active);
+  };
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    if ((st = launch_residual(c, DG_FP64, B_X, B_HX, 0, active))) return st;
+    if ((st = launch_check(c, active, tol))) return st;
+    int cnt[4];
+    if ((st = read_counts(c, cnt))) return st;
+    if (cnt[1] > 0) {
+      set_error("non-finite residual in " + std::to_string(cnt[1]) + " element(s)");
+      return DG_ERR_NUMERIC;
+    }
+    if (cnt[0] == 0) {
+      // every element converged: an FP64 Rayleigh-Ritz step on span(X) (HX = H X is
+      // exact) gives the orthonormal Ritz basis, whose residuals are checked again
+      if ((st = activate_all())) return st;
+      if ((st = rr_and_rotate(c, DG_FP64, 1, active, false))) return st;
+      have_p = false;   // the Rayleigh-Ritz step on span(X) leaves no search direction
+      if ((st = launch_residual(c, DG_FP64, B_X, B_HX, 0, active))) return st;
+      if ((st = launch_check(c, active, tol))) return st;
+      if ((st = read_counts(c, cnt))) return st;
+      if (c.log_level > 0) fprintf(stderr, "[dg] mixed refine it=%d: %d element(s) above tol after the FP64 Rayleigh-Ritz step\n", it, cnt[0]);
+      if (cnt[0] == 0) break;
+    }
+    {
+      std::vector<int> act(c.n_elem);
+      if ((st = sync_read(c, act.data(), active, sizeof(int) * c.n_elem))) return st;
+      c.active_host = act;
+    }
+    if (c.log_level > 0) {
+      std::vector<double> mr(c.n_elem);
+      if ((st = sync_read(c, mr.data(), c.dev_maxres, sizeof(double) * c.n_elem))) return st;
+      double m = 0.0;
+      for (int e = 0; e < c.n_elem; ++e) m = std::max(m, c.active_host[e] ? mr[e] : 0.0);
+      fprintf(stderr, "[dg] mixed refine it=%d active=%d max_res=%.3e\n", it, cnt[0], m);
+    }
+    if ((st = step(have_p ? 3 : 2))) return st;
+    have_p = true;
+  }
+  c.active_host.clear();
+  if ((st = activate_all())) return st;
+  c.active_host.clear();
+  if (iters && (st = sync_read(c, iters, c.dev_iters, sizeof(int) * c.n_elem))) return st;
+  if ((st = launch_residual(c, DG_FP64, B_X, B_HX, 0, active))) return st;
+  if ((st = launch_check(c, active, tol))) return st;
+  int cnt[4];
+  if ((st = read_counts(c, cnt))) return st;
+  *n_done = c.n_elem - cnt[0];
+  if (cnt[1] > 0) {
+    set_error("non-finite residual in " + std::to_string(cnt[1]) + " element(s)");
+    return DG_ERR_NUMERIC;
+  }
+  c.last_breakdowns = cnt[2];
+  return DG_OK;
+}
+
 int run_chfsi(Ctx& c, int prec, double tol, int max_iter, int degree, int* iters, int* n_done);
 
 int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* iters) {
@@ -420,18 +583,25 @@ int solve(Ctx& c, const dg_solve_params* p, double* eig, double* resid, int* ite
                                 : run_chfsi(c, DG_FP32, std::max(tmp, p->tol), p->max_iter, p->cheb_degree,
                                             it1.data(), &done);
     if (st < 0) return st;
-    // promote X (into W's storage) and, for LOBPCG, the last search direction P (into
-    // T1, which the start rotation turns into P) to FP64, then FP64 refinement sweeps
+    // promote X (into W's storage) to FP64
     if ((st = launch_convert(c, B_X, DG_FP32, B_W, DG_FP64, KC_K))) return st;
     const bool carry = p->method == DG_LOBPCG;
-    if (carry && (st = launch_convert(c, B_P, DG_FP32, B_T1, DG_FP64, KC_K))) return st;
-    {
+    if (carry && c.mixed_refine) {
+      // the FP32 search direction P moves to T1 (the start rotation turns T1 into P)
+      int perm[kMaxBlocks] = {B_W, B_X, B_T1, B_HX, B_HW, B_HP, B_T0, B_P};
+      if ((st = launch_permute(c, perm, nullptr))) return st;
+      st = run_mixed_refine(c, p->tol, p->max_iter, it2.data(), &done);
+      if (st < 0) return st;
+    } else {
+      // and, for LOBPCG, the last search direction P (into T1, which the start rotation
+      // turns into P), then FP64 refinement sweeps
+      if (carry && (st = launch_convert(c, B_P, DG_FP32, B_T1, DG_FP64, KC_K))) return st;
       int perm[kMaxBlocks] = {B_W, B_X, B_P, B_HX, B_HW, B_HP, B_T0, B_T1};
       if ((st = launch_permute(c, perm, nullptr))) return st;
+      st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry, std::max(0, p->graph_iters),
+                      false);
+      if (st < 0) return st;
     }
-    st = run_lobpcg(c, DG_FP64, p->tol, p->max_iter, it2.data(), &done, carry, std::max(0, p->graph_iters),
-                    false);
-    if (st < 0) return st;
   }
   if (done < c.n_elem && c.last_breakdowns > 0) {
     set_error(std::to_string(c.n_elem - done) + " element(s) did not converge after " +

@@ -90,9 +90,11 @@ def _check_eigs(name, refs, ks, eigs, iters, tag):
     return worst
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_c2_every_element_eigenvalues(precision):
-    """All 16 elements of the 4x4 slab in one batch, FP64 and mixed, to 1e-8."""
+@pytest.mark.parametrize("precision,refine", [(0, 0), (1, 0), (1, 1)])
+def test_c2_every_element_eigenvalues(precision, refine, monkeypatch):
+    """All 16 elements of the 4x4 slab in one batch, FP64 and mixed (FP64 refinement;
+    refine = 1: the refinement with FP32 search blocks), to 1e-8."""
+    monkeypatch.setenv("DG_MIXED_REFINE", str(refine))
     refs = _refs("c2")
     cfg = W.make_config("c2")
     ks = [k for k in range(cfg.n_elem) if str(k) in refs["elements"]]
