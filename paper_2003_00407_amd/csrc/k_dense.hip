@@ -798,7 +798,8 @@ struct RRArgs {
   double hp_tol;
 };
 
-constexpr int kRRThreads = 512;
+constexpr int kRRThreads = 512;     // LDS variant (orders up to kRRLdsOrder)
+constexpr int kRRThreadsL2 = 1024;  // L2-resident variant: more loads in flight for its latency-bound sweeps
 constexpr int kTriMax = 272;   // largest projected problem handled (3 x 88 + pad)
 
 // ---------------------------------------------------------------------------
@@ -823,7 +824,7 @@ constexpr int kRRLdsOrder = 132;                  // np * np doubles fit in kRRL
 __device__ __forceinline__ int refl_off(int kk, int m) { return kk * (m - 1) - kk * (kk - 1) / 2; }
 
 template <bool kLds>
-__global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
+__global__ void __launch_bounds__(kLds ? kRRThreads : kRRThreadsL2) k_rr_lds(RRArgs A) {
   const int e = blockIdx.x;
   const ElemDev& E = A.elems[e];
   if (A.active && !A.active[e]) {
@@ -1077,8 +1078,9 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
   // ---- Householder tridiagonalisation in LDS; reflector kk kept in column kk below the diagonal
   const int m = n;
   __shared__ int skip;
-  __shared__ double pq[2][kTriMax];
-  static_assert(kRRThreads == 512, "the product p = tau A v splits the rows between two sets of 256 threads");
+  // the product p = tau A v splits the rows between sets of 256 threads
+  constexpr int kSets = (kLds ? kRRThreads : kRRThreadsL2) / 256;
+  __shared__ double pq[kSets][kTriMax];
   for (int kk = 0; kk < m - 2; ++kk) {
     const int mr = m - kk - 1;
     if (wv == 0) {
@@ -1107,7 +1109,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     // p = tau A v; A is symmetric, so row i is read as column i (consecutive threads,
     // consecutive addresses): two threads per row, each over half of the rows
     {
-      const int q = tid >> 8, qn = (mr + 1) >> 1;
+      const int q = tid >> 8, qn = (mr + kSets - 1) / kSets;
       const int j0 = q * qn, j1 = min(mr, j0 + qn);
       for (int i = tid & 255; i < mr; i += 256) {
         const double* col = L + (kk + 1) * np + kk + 1 + i;
@@ -1120,7 +1122,10 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_lds(RRArgs A) {
     if (wv == 0) {
       double kp = 0.0;
       for (int i = lane; i < mr; i += 64) {
-        const double p = tau * (pq[0][i] + pq[1][i]);
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSets; ++q) p += pq[q][i];
+        p *= tau;
         ps[i] = p;
         kp += vs[i] * p;
       }
@@ -2590,7 +2595,7 @@ int launch_rr(Ctx& c, int nb, int kfix, int nkeep, int mode, const int* active) 
   if (in_lds) {
     hipLaunchKernelGGL(k_rr_lds<true>, dim3(c.n_elem), dim3(kRRThreads), need, c.stream, a);
   } else {
-    hipLaunchKernelGGL(k_rr_lds<false>, dim3(c.n_elem), dim3(kRRThreads), 0, c.stream, a);
+    hipLaunchKernelGGL(k_rr_lds<false>, dim3(c.n_elem), dim3(kRRThreadsL2), 0, c.stream, a);
   }
   DG_HIP(hipGetLastError());
   return DG_OK;

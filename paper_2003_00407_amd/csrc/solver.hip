@@ -290,11 +290,14 @@ static int run_lobpcg(Ctx& c, int prec, double tol, int max_iter, int* iters, in
       if (c.log_level >= 2 && it % 10 == 1) {
         std::vector<long long> ph(16 * c.n_elem);
         if ((st = sync_read(c, ph.data(), c.dev_phase, sizeof(long long) * 16 * c.n_elem))) return st;
-        // wall clock at 100 MHz; element 0
+        // wall clock at 100 MHz; the element whose step took longest
         static const char* names[9] = {"chol", "zinv", "matmul", "tridiag", "bisect", "invit", "mgs", "back",
                                        "coeff"};
-        fprintf(stderr, "[dg] rr phases (us):");
-        for (int k = 0; k < 9; ++k) fprintf(stderr, " %s %.0f", names[k], (ph[k + 1] - ph[k]) / 100.0);
+        int es = 0;
+        for (int e = 1; e < c.n_elem; ++e)
+          if (ph[16 * e + 9] - ph[16 * e] > ph[16 * es + 9] - ph[16 * es]) es = e;
+        fprintf(stderr, "[dg] rr phases (us), element %d of order %d:", es, 3 * c.K[es]);
+        for (int k = 0; k < 9; ++k) fprintf(stderr, " %s %.0f", names[k], (ph[16 * es + k + 1] - ph[16 * es + k]) / 100.0);
         fprintf(stderr, "\n");
       }
     }
