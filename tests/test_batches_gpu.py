@@ -86,3 +86,27 @@ def test_c4_uneven_batch_mixed():
     js = [e.n_states for e in els]
     sample = sorted(set(pick.values()) | {int(np.argmin(js)), int(np.argmax(js))})
     _certify(E, D, els, eig, sample, "c4")
+
+
+def test_c4_captured_graph_matches_eager():
+    """The whole C4 batch in FP64, eager and with four LOBPCG steps per HIP graph
+    replay (one graph per element group): the same eigenvalues to 1e-10 Ha, both at
+    the 1e-8 residual, graph iteration counts at most three steps longer."""
+    torch = need_torch_cuda()
+    from paper_2003_00407_amd import dgalb as D
+    cfg = W.make_config("c4")
+    els = cfg.elements
+    print(f"[c4 graph] {len(els)} elements, creating", flush=True)
+    E = D.Elements(els)
+    off_x0 = E.offsets(D.DG_OFF_X0)
+    gen = torch.Generator(device="cuda").manual_seed(cfg.x0_seed_base)
+    x0 = torch.randn(int(off_x0[-1]), dtype=torch.float64, device="cuda", generator=gen)
+    eig0, res0, it0, st0 = E.solve(x0, tol=1e-8)
+    print(f"[c4 graph] eager: status {st0}, iterations {it0.min()}..{it0.max()}", flush=True)
+    eig1, res1, it1, st1 = E.solve(x0, tol=1e-8, graph_iters=4)
+    print(f"[c4 graph] graph: status {st1}, iterations {it1.min()}..{it1.max()}, "
+          f"max |eig difference| {torch.max(torch.abs(eig0 - eig1)).item():.1e}", flush=True)
+    assert st0 == 0 and st1 == 0
+    assert res0.max().item() <= 1e-8 and res1.max().item() <= 1e-8
+    assert torch.max(torch.abs(eig0 - eig1)).item() < 1e-10
+    assert np.all(it1 >= it0) and np.all(it1 - it0 <= 3)
