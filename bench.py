@@ -42,8 +42,8 @@ METRIC = "ALB element-solves/s + Hψ GB/s, mixed vs FP64 on one GPU at 1e-8 Ha e
 PMC_TRAFFIC = {
     # profiles/c4_fp64_hbm_traffic.md: one-stream C4, Gram class (k_gram + k_gram_reduce) per call
     "gram": {"config": "c4/1", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-             "sha256": "3b0f3be512e5db0ec0a3f2ed9cd22ee7d2c43b5f2bde6859f23c94202dc8c6e1",
-             "bytes_per_launch": 186450298314},
+             "sha256": "e7ae9f336d575d0144818ff8fd3110d8e24912c5cfd5ecaf183ce81247bf39c0",
+             "bytes_per_launch": 186447210093},
 }
 
 
