@@ -38,12 +38,16 @@ METRIC = "ALB element-solves/s + Hψ GB/s, mixed vs FP64 on one GPU at 1e-8 Ha e
 # HBM bytes per launch from `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of
 # the instrumented step (profiles/*_hbm_traffic.md), scaled by what the counters read
 # for a 1 GiB device copy of the same run.  Valid only for the kernel source and
-# workload they were taken on: `traffic` is reported null once the source differs.
+# workload they were taken on: `traffic` is reported null once any of the sources that
+# fix the kernels and the workload's shapes (the kernel file, the context plan with the
+# guard rule, the input generators) differs.
 PMC_TRAFFIC = {
     # profiles/c4_fp64_hbm_traffic.md: one-stream C4, Gram class (k_gram + k_gram_reduce) per call
-    "gram": {"config": "c4/1", "source": "paper_2003_00407_amd/csrc/k_dense.hip",
-             "sha256": "e7ae9f336d575d0144818ff8fd3110d8e24912c5cfd5ecaf183ce81247bf39c0",
-             "bytes_per_launch": 186447210093},
+    "gram": {"config": "c4/1",
+             "source": ["paper_2003_00407_amd/csrc/k_dense.hip", "paper_2003_00407_amd/csrc/runtime.hip",
+                        "workloads/__init__.py"],
+             "sha256": "79189e84464e9d8b358d53c4c53c961a316af2aaf671714964dd442ee5fd3c17",
+             "bytes_per_launch": 214595375967},
 }
 
 
@@ -138,9 +142,15 @@ def kernel_table(r):
     return tab
 
 
-def source_sha(path):
-    with open(os.path.join(HERE, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def source_sha(paths):
+    """sha256 of one file, or of the concatenated per-file digests of a list."""
+    if isinstance(paths, str):
+        with open(os.path.join(HERE, paths), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(source_sha(p).encode())
+    return h.hexdigest()
 
 
 def roofline_for(r, config, with_traffic=True, mixed=False):

@@ -97,7 +97,8 @@ typedef struct {
 } dg_element_desc;
 
 typedef struct {
-  int32_t n_guard;        /* guard states carried above J_k; < 0: max(4, ceil(J_k/10)) */
+  int32_t n_guard;        /* guard states carried above J_k; < 0: max(4, ceil(J_k/5)),  */
+                          /* reduced (not below 4) where J_k + guards would pass 88     */
   int32_t max_cheb_degree;/* largest Chebyshev degree used by dg_band_energy (0: none)  */
   int32_t ckpt_stride;    /* checkpoint every ckpt_stride filter steps (>= 1)           */
   int32_t n_streams;      /* element groups solved concurrently, each on its own HIP     */

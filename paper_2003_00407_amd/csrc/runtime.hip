@@ -248,7 +248,9 @@ static int make_plan(int n_elem, const dg_element_desc* d, const dg_options* opt
   for (int e = 0; e < n_elem; ++e) {
     ElemPlan& p = P.el[e];
     p.J = d[e].n_states;
-    p.G = guard_opt >= 0 ? guard_opt : std::max(4, (int)std::ceil(0.1 * p.J));
+    // default: a fifth of J (at least 4), fewer where J + guards would pass 88
+    p.G = guard_opt >= 0 ? guard_opt : std::max(4, (int)std::ceil(0.2 * p.J));
+    if (guard_opt < 0 && p.J + p.G > 88) p.G = std::max(4, 88 - p.J);
     p.K = p.J + p.G;
     p.N = d[e].n[0] * d[e].n[1] * d[e].n[2];
     if (p.K > 88 || p.K > p.N / 2) {

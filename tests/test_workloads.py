@@ -67,4 +67,5 @@ def test_initial_block_seeded():
     a = W.initial_block(100, 5, seed=3)
     b = W.initial_block(100, 5, seed=3)
     assert a.shape == (5, 100) and np.array_equal(a, b)
-    assert W.guard_count(40) == 4 and W.guard_count(60) == 6
+    assert W.guard_count(40) == 8 and W.guard_count(60) == 12 and W.guard_count(8) == 4
+    assert W.guard_count(80) == 8 and W.guard_count(84) == 4   # J + guards <= 88

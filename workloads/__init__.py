@@ -181,8 +181,10 @@ class Config:
 
 
 def guard_count(j: int) -> int:
-    """Number of guard states carried above the J wanted ones."""
-    return max(4, int(math.ceil(0.1 * j)))
+    """Number of guard states carried above the J wanted ones: a fifth of J (at least
+    4), fewer where J + guards would pass the solver's 88 columns."""
+    g = max(4, int(math.ceil(0.2 * j)))
+    return g if j + g <= 88 else max(4, 88 - j)
 
 
 # --------------------------------------------------------------------------
