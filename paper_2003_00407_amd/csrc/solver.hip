@@ -71,6 +71,25 @@ int apply_h(Ctx& c, int elem, int n_vec, int prec, const void* x, long long ldx,
 // ---------------------------------------------------------------------------
 // LOBPCG (Algorithm 1) for every element at once
 // ---------------------------------------------------------------------------
+// HP' = H P' (P' in p_blk, into hp_blk) for the elements the last Rayleigh-Ritz step
+// flagged as nearly dependent (every active element with DG_FRESH_HP=1); the others
+// keep the rotated HP' already in hp_blk
+static int launch_hp_afresh(Ctx& c, int prec, int p_blk, int hp_blk, const int* active) {
+  const int* mask = (c.fresh_hp_all || !c.dev_hpflag) ? active : c.dev_hpflag;
+  std::vector<int> saved;
+  const bool account = mask == c.dev_hpflag && c.timing && !c.capturing;
+  if (account) {
+    // per-kernel byte accounting counts the flagged elements only
+    std::vector<int> fl(c.n_elem);
+    if (int st = sync_read(c, fl.data(), c.dev_hpflag, sizeof(int) * c.n_elem)) return st;
+    saved = c.active_host;
+    c.active_host = fl;
+  }
+  const int st = launch_hpsi(c, -1, 0, prec, p_blk, hp_blk, mask);
+  if (account) c.active_host = saved;
+  return st;
+}
+
 static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpcg) {
   int st;
   ColSet S{nb, {B_X, B_W, B_P}};
@@ -107,21 +126,7 @@ static int rr_and_rotate(Ctx& c, int prec, int nb, const int* active, bool lobpc
   ra.out_blk[0] = B_X;
   ra.out_blk[1] = B_P;
   if ((st = launch_rotate(c, prec, ra))) return st;
-  if (two) {
-    const int* mask = (c.fresh_hp_all || !c.dev_hpflag) ? active : c.dev_hpflag;
-    std::vector<int> saved;
-    const bool account = mask == c.dev_hpflag && c.timing && !c.capturing;
-    if (account) {
-      // per-kernel byte accounting counts the flagged elements only
-      std::vector<int> fl(c.n_elem);
-      if ((st = sync_read(c, fl.data(), c.dev_hpflag, sizeof(int) * c.n_elem))) return st;
-      saved = c.active_host;
-      c.active_host = fl;
-    }
-    st = launch_hpsi(c, -1, 0, prec, B_T1, B_P, mask);
-    if (account) c.active_host = saved;
-    if (st) return st;
-  }
+  if (two && (st = launch_hp_afresh(c, prec, B_T1, B_P, active))) return st;
   // new X = T0, P = T1, HX = X, HP = P, T0 = HX, T1 = HP
   int perm[kMaxBlocks] = {B_T0, B_W, B_T1, B_X, B_HW, B_P, B_HX, B_HP};
   return launch_permute(c, perm, active);
@@ -434,20 +439,7 @@ static int run_mixed_refine(Ctx& c, double tol, int max_iter, int* iters, int* n
     ra.out_blk[0] = B_T0;
     if ((s2 = launch_rotate(c, DG_FP32, ra))) return s2;
     // H P' afresh (FP32) where the basis was nearly dependent
-    {
-      const int* mask = (c.fresh_hp_all || !c.dev_hpflag) ? active : c.dev_hpflag;
-      std::vector<int> saved;
-      const bool account = mask == c.dev_hpflag && c.timing && !c.capturing;
-      if (account) {
-        std::vector<int> fl(c.n_elem);
-        if ((s2 = sync_read(c, fl.data(), c.dev_hpflag, sizeof(int) * c.n_elem))) return s2;
-        saved = c.active_host;
-        c.active_host = fl;
-      }
-      s2 = launch_hpsi(c, -1, 0, DG_FP32, B_T1, B_T0, mask);
-      if (account) c.active_host = saved;
-      if (s2) return s2;
-    }
+    if ((s2 = launch_hp_afresh(c, DG_FP32, B_T1, B_T0, active))) return s2;
     // X' = X C_X + P' into W (FP64)
     RotArgs rx{};
     rx.active = active;
